@@ -1,0 +1,307 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the jerk-search matched filter on one MI355X.
+
+A step is one full search of the 2^22-bin spectrum (2^23 float32 samples,
+four seeded tones) over the 201 x 61 = 12261-template lattice (zmax 200,
+wmax 600, dz 2, dw 20) with half-bin r spacing: 1.03e11 plane points. The
+plane (411 GB in FP32) does not fit in HBM, so each step writes it as slabs
+of template rows into one resident slab buffer (every point is written to
+HBM; later slabs overwrite earlier ones). Inputs and the template bank are in
+HBM before the timed region; template generation is timed separately.
+
+Prints one JSON line (see the keys below). ``--gpus`` above 1 is refused:
+this build runs on one GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+MFMA_BF16_TFLOPS = 2500.0
+MFMA_FP16_TFLOPS = 2500.0
+# FP32 vector FMA without packed (dual) FP32 issue: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz.
+FP32_VECTOR_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--path", default="auto", choices=["auto", "fft", "split_bf16", "fp16"])
+    ap.add_argument("--slab-gb", type=float, default=16.0, help="slab buffer size (GB)")
+    ap.add_argument("--compare-paths", type=int, default=1,
+                    help="also time the FP32 and split-BF16 paths alone (steps each)")
+    ap.add_argument("--cpu-templates", type=int, default=8,
+                    help="templates (full rows) in the oracle's timed sample; 0 skips cpu_baseline")
+    ap.add_argument("--errors", type=int, default=1, help="measure plane errors on the 2^15-bin search")
+    return ap.parse_args()
+
+
+def kernel_name(g):
+    if g["path"] == 0:
+        return f"fft_correlate_kernel<S={g['seg_len']}>"
+    return "gemm_correlate_kernel<split_bf16>" if g["path"] == 1 else "gemm_correlate_kernel<fp16>"
+
+
+def launch_counts(g, m, nbins):
+    """Algorithmic work of one launch of group g over m templates and nbins bins.
+
+    FFT path (FP32 vector): per segment one forward FFT per template block, per
+    (segment, template, phase) a complex multiply (6S), an inverse FFT
+    (5 S log2 S) and the power of the U kept lags (3U); nominal FFT counts.
+    MFMA path: 8 K real flops per output point per product (3 products for
+    split-BF16, 1 for FP16).
+    Bytes: 4 per plane point written plus 8 per spectrum bin read.
+    """
+    points = 2 * nbins * m
+    bytes_ = 4 * points + 8 * nbins
+    if g["path"] == 0:
+        S, K, tpb = g["seg_len"], g["taps"], g["templates_per_block"]
+        U = S - K + 1
+        n_seg = math.ceil(nbins / U)
+        n_tb = math.ceil(m / tpb)
+        fft = 5 * S * math.log2(S)
+        flops = n_seg * (n_tb * fft + m * 2 * (6 * S + fft + 3 * U))
+    else:
+        flops = points * 8 * g["taps"] * (3 if g["path"] == 1 else 1)
+    return points, flops, bytes_
+
+
+def source_sha(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1911_01353_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kname, launch_points_avg):
+    """HBM bytes per launch from the committed counter summary, if it matches the current source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        ent = data.get(kname)
+        if not ent or ent.get("source_sha") != source_sha(ent["sources"]):
+            return None
+        return ent["bytes_per_point"] * launch_points_avg
+    except Exception:
+        return None
+
+
+def run_search_steps(J, torch, plan, bank, spec, slab, rows, steps, timing):
+    """Runs `steps` full searches; records (group, t0, t1, start_event, end_event) when timing."""
+    info = plan.info()
+    T = info["n_templates"]
+    G = info["n_groups"]
+    recs = []
+    for _ in range(steps):
+        for t0 in range(0, T, rows):
+            t1 = min(T, t0 + rows)
+            for g in range(G):
+                if timing:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                plan.search_group(bank, spec, slab, g, t0, t1)
+                if timing:
+                    e1.record()
+                    recs.append((g, t0, t1, e0, e1))
+    return recs
+
+
+def time_path(J, torch, spec, n, path, steps, warmup, slab_gb, want_kernels):
+    plan = J.Plan(n, 200.0, 600.0, 2.0, 20.0, path=path)
+    info = plan.info()
+    bank = plan.new_bank()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.build_templates(bank)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    T = info["n_templates"]
+    row_bytes = 2 * n * 4
+    rows = max(1, min(T, int(slab_gb * 1e9 // row_bytes)))
+    slab = torch.empty((rows, 2 * n), dtype=torch.float32, device="cuda")
+    run_search_steps(J, torch, plan, bank, spec, slab, rows, warmup, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = run_search_steps(J, torch, plan, bank, spec, slab, rows, steps, want_kernels)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    groups = plan.groups()
+    members = plan.members()
+    out = {"plan": plan, "wall": wall, "t_build": t_build, "T": T, "rows": rows, "kernels": None,
+           "groups": groups}
+    if want_kernels:
+        agg = {}
+        for g, a, b, e0, e1 in recs:
+            gi = groups[g]
+            ms = members[gi["first_member"]: gi["first_member"] + gi["n_members"]]
+            m = int(((ms >= a) & (ms < b)).sum())
+            if m == 0:
+                continue
+            ms_t = e0.elapsed_time(e1) * 1e-3
+            pts, fl, by = launch_counts(gi, m, n)
+            k = kernel_name(gi)
+            d = agg.setdefault(k, {"launches": 0, "time": 0.0, "points": 0, "flops": 0.0, "bytes": 0.0,
+                                   "path": gi["path"]})
+            d["launches"] += 1
+            d["time"] += ms_t
+            d["points"] += pts
+            d["flops"] += fl
+            d["bytes"] += by
+        out["kernels"] = agg
+    return out
+
+
+def cpu_baseline(spec, n_templates_sample):
+    """The FP64 oracle, single-threaded, on full rows of a sample of templates."""
+    import numpy as np
+    from oracle import Grid, oracle_plane
+    grid = Grid(200.0, 600.0, 2.0, 20.0)
+    ts = [int(t) for t in np.linspace(0, grid.n_templates - 1, n_templates_sample)]
+    t0 = time.perf_counter()
+    plane = oracle_plane(spec, grid, templates=ts)
+    dt = time.perf_counter() - t0
+    pts = plane.size
+    return {"value": pts / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(ts)} full rows (2^23 points each, templates {ts}) of the 2^22-bin search, "
+                      f"FP64 numpy direct correlation incl. template quadrature, {dt:.1f} s"}
+
+
+def plane_errors(J, torch):
+    """Max/RMS floored relative power error of each path on the full 2^15-bin plane."""
+    import numpy as np
+    import synth
+    from oracle import Grid, error_summary, oracle_plane, peak_index
+    cfg = synth.CONFIGS["c1"]
+    spec_np = synth.make_spectrum(cfg)
+    grid = Grid(cfg.zmax, cfg.wmax, cfg.dz, cfg.dw)
+    ora = oracle_plane(spec_np, grid)
+    spec = torch.from_numpy(spec_np).cuda()
+    res = {}
+    for path in ("fft", "split_bf16", "fp16"):
+        plan = J.Plan(spec_np.shape[0], cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
+        bank = plan.new_bank()
+        plan.build_templates(bank)
+        plane = torch.empty((grid.n_templates, 2 * spec_np.shape[0]), dtype=torch.float32, device="cuda")
+        plan.search(bank, spec, plane)
+        torch.cuda.synchronize()
+        got = plane.cpu().numpy()
+        s = error_summary(got, ora)
+        res[path] = {"max": s["max"], "rms": s["rms"], "peak_match": peak_index(got) == peak_index(ora)}
+        plan.close()
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "detail": "sharding by template range, r range or spectrum is described in the "
+                                    "design notes; no multi-GPU path is built"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1911_01353_amd as J
+    import synth
+
+    J.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = synth.CONFIGS["c2"]
+    spec_np = synth.make_spectrum(cfg)
+    n = spec_np.shape[0]
+    spec = torch.from_numpy(spec_np).cuda()
+    print(f"[bench] spectrum {n} bins ready; path {args.path}", file=sys.stderr, flush=True)
+
+    main_res = time_path(J, torch, spec, n, args.path, args.steps, args.warmup, args.slab_gb, True)
+    T = main_res["T"]
+    points_per_step = 2 * n * T
+    wall = main_res["wall"]
+    value = points_per_step * args.steps / wall
+    print(f"[bench] {args.path}: {value:.3e} points/s ({wall / args.steps * 1e3:.1f} ms/step)", file=sys.stderr,
+          flush=True)
+
+    # dominant kernel roofline
+    ks = main_res["kernels"]
+    dom = max(ks, key=lambda k: ks[k]["time"])
+    d = ks[dom]
+    avg_t = d["time"] / d["launches"]
+    kernel_share = d["time"] / sum(v["time"] for v in ks.values())
+    if d["path"] == 0:
+        achieved = d["flops"] / d["launches"] / avg_t / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_TFLOPS, "unit": "TFLOP/s"}
+    else:
+        achieved = d["flops"] / d["launches"] / avg_t / 1e12
+        roof = {"bound": "mfma", "achieved": achieved,
+                "peak": MFMA_BF16_TFLOPS if d["path"] == 1 else MFMA_FP16_TFLOPS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic_from_profiles(dom, d["points"] / d["launches"])
+    roof["kernel"] = dom
+    roof["kernel_time_share"] = kernel_share
+    roof["hbm_GBps"] = d["bytes"] / d["time"] / 1e9
+    roof["hbm_frac"] = roof["hbm_GBps"] / HBM_PEAK_GBS
+    roof["avg_launch_ms"] = avg_t * 1e3
+    roof["launches"] = d["launches"]
+    kernels_out = {k: {"launches": v["launches"], "time_s": v["time"], "points_per_s": v["points"] / v["time"],
+                       "tflops": v["flops"] / v["time"] / 1e12, "hbm_GBps": v["bytes"] / v["time"] / 1e9}
+                   for k, v in ks.items()}
+
+    paths = {args.path: value}
+    if args.compare_paths:
+        for p in ("fft", "split_bf16"):
+            if p == args.path:
+                continue
+            r = time_path(J, torch, spec, n, p, max(1, args.steps // 2), 1, args.slab_gb, False)
+            paths[p] = points_per_step * max(1, args.steps // 2) / r["wall"]
+            print(f"[bench] {p}: {paths[p]:.3e} points/s", file=sys.stderr, flush=True)
+            r["plan"].close()
+
+    errors = plane_errors(J, torch) if args.errors else None
+    cpu = cpu_baseline(spec_np, args.cpu_templates) if args.cpu_templates > 0 else None
+
+    line = {
+        "metric": "(r,z,w) plane points/s",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"auto": "f32+bf16x3", "fft": "f32", "split_bf16": "bf16x3", "fp16": "f16"}[args.path],
+        "data": "synthetic",
+        "config": {"workload": "single search, 2^22 bins (2^23 float32 samples, 4 seeded tones), "
+                               "zmax 200, wmax 600, dz 2, dw 20 (201x61=12261 templates), half-bin r, "
+                               f"path {args.path}, plane written as {main_res['rows']}-row slabs",
+                   "nbins": n, "templates": T, "points_per_step": points_per_step},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "paths_points_per_s": paths,
+        "plane_error_2e15_bins": errors,
+        "template_build_s": main_res["t_build"],
+        "kernels": kernels_out,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

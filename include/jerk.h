@@ -1,0 +1,159 @@
+/*
+ * jerk.h - C ABI of the MI355X (gfx950) Fourier-domain "jerk" search matched filter.
+ *
+ * The library correlates a complex spectrum with a bank of response templates,
+ * one per (zbar, w) pair of a lattice, and writes the (r, z, w) power plane
+ * (Adamek, Novotny, Dimoudi, Armour, arXiv:1911.01353, section
+ * "Implementation": each filter fits the Fourier response for a given first
+ * frequency derivative z = fdot T^2 and second frequency derivative
+ * w = fddot T^3; Figure 1: the correlation is evaluated by overlap-and-save).
+ *
+ * Definitions used by every entry point
+ * -------------------------------------
+ *  Spectrum      X[k], k = 0..nbins-1, complex64 interleaved (re, im) float pairs,
+ *                in device memory. X[k] is taken as 0 outside [0, nbins).
+ *  Lattice       zbar_i = -zmax + i dz, i < n_z = floor(2 zmax / dz) + 1;
+ *                w_j = (j - J) dw, j < n_w = 2J + 1, J = floor(wmax / dw);
+ *                template t = j * n_z + i (w-major).
+ *  Response      T(qbar; zbar, w) = R(qbar - zbar/2 + w/12; zbar - w/2, w),
+ *                R(q; z, w) = integral_0^1 exp(2 pi i (q u + z u^2/2 + w u^3/6)) du
+ *                (zbar, rbar are observation averages of fdot and frequency).
+ *  Half-width    h_t = ceil(|zbar|/2 + |w|/12) + margin_bins; 2 h_t taps.
+ *  Plane         for p = 2 k0 + phase (r = p / 2), p in [0, 2 nbins):
+ *                P[t][p] = | sum_{k=k0-h_t+1}^{k0+h_t} X[k] conj(T(k0 + phase/2 - k)) |^2
+ *                stored as float32, row t at plane + (t - t_begin) * ld.
+ *
+ * Conventions
+ * -----------
+ *  - Every function returns an int32 status: JERK_OK (0) or a negative code.
+ *    Arguments are checked before any work is queued; on error nothing is queued
+ *    and jerk_last_error() (per thread) describes the problem.
+ *  - The caller owns all device memory and streams. The library never allocates
+ *    device memory on the search path; it states the sizes it needs
+ *    (jerk_plan_info) and works in caller buffers. Work is queued on the caller's
+ *    stream and returns before it completes; buffers must stay valid until the
+ *    stream work ends. Device faults surface at the caller's next synchronisation.
+ *  - Plan and server objects are opaque host handles, freed by *_destroy.
+ */
+#ifndef JERK_H
+#define JERK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define JERK_OK 0
+#define JERK_EINVAL (-1)       /* an argument is invalid                         */
+#define JERK_ENOMEM (-2)       /* a caller buffer is too small / never fits      */
+#define JERK_EAGAIN (-3)       /* queue full, retry later                        */
+#define JERK_EPENDING (-4)     /* request not finished yet                       */
+#define JERK_EHIP (-5)         /* a HIP runtime call failed                      */
+#define JERK_EUNSUPPORTED (-6) /* valid but not supported by this build          */
+#define JERK_EINTERNAL (-7)    /* library bug                                    */
+
+/* ---- correlation paths ------------------------------------------------- */
+#define JERK_PATH_FFT_FP32 0       /* fused overlap-save FFT, FP32                  */
+#define JERK_PATH_GEMM_SPLIT_BF16 1 /* direct correlation on MFMA, split-BF16 hi+lo  */
+#define JERK_PATH_GEMM_FP16 2      /* direct correlation on MFMA, FP16              */
+#define JERK_PATH_AUTO 3           /* per width group: the faster of FFT / split-BF16 */
+
+/* Human-readable name of a status code (static string). */
+const char* jerk_status_str(int32_t status);
+/* Last error message of the calling thread (valid until its next library call). */
+const char* jerk_last_error(void);
+/* Library version string, e.g. "jerk-mi355x 1.0 gfx950". */
+const char* jerk_version(void);
+
+/* ---- plans -------------------------------------------------------------- */
+typedef struct jerk_plan jerk_plan;
+
+typedef struct jerk_plan_desc {
+  int64_t nbins;               /* spectrum length the plan is sized for, >= 1          */
+  double zmax, wmax;           /* lattice extents (>= 0)                               */
+  double dz, dw;               /* lattice steps (> 0; dw may be 0 only if wmax == 0)   */
+  int32_t numbetween;          /* outputs per bin: must be 2 (half-bin r spacing)      */
+  int32_t margin_bins;         /* half-width margin M (0..256), usually 16             */
+  int32_t path;                /* JERK_PATH_*                                          */
+  int32_t seg_len;             /* FFT segment length (512, 1024, 2048, 4096) or 0       */
+  int32_t templates_per_block; /* FFT path templates per workgroup (1..64) or 0         */
+  int32_t tap_quantum;         /* width-group granularity in taps (16..512, mult of 16) or 0 */
+  uint32_t flags;              /* reserved, must be 0                                  */
+} jerk_plan_desc;
+
+typedef struct jerk_plan_info_t {
+  int32_t n_z, n_w, n_templates, n_groups;
+  int64_t nbins;          /* as in the descriptor                                    */
+  int64_t n_r;            /* outputs per row = 2 * nbins                              */
+  int32_t max_taps;       /* largest 2 h_t                                            */
+  int32_t path;           /* path of the descriptor                                  */
+  size_t bank_bytes;      /* device bytes of the template bank                       */
+  size_t workspace_bytes; /* device workspace jerk_search needs (may be 0)           */
+  size_t plane_row_bytes; /* 4 * n_r                                                 */
+  size_t taps_offset;     /* byte offset in the bank of the FP64 taps (see group info) */
+} jerk_plan_info_t;
+
+typedef struct jerk_group_info_t {
+  int32_t taps;                /* K_g: taps of every template of the group (even)        */
+  int32_t seg_len;             /* FFT segment length S_g                                */
+  int32_t templates_per_block; /* FFT path templates per workgroup                      */
+  int32_t path;                /* resolved path (FFT_FP32, GEMM_SPLIT_BF16 or GEMM_FP16) */
+  int32_t n_members;           /* templates in the group                                */
+  int32_t first_member;        /* index of its first entry in jerk_plan_members order   */
+  size_t taps_offset;          /* bank byte offset of the group's FP64 taps:
+                                  complex128 [n_members][2 phases][taps], tap j multiplies
+                                  bin k0 - taps/2 + 1 + j; taps outside the template's own
+                                  2 h_t window are 0                                     */
+} jerk_group_info_t;
+
+/* Builds the lattice, half-widths, width groups and bank layout. Host only.
+ * EINVAL for an invalid descriptor (non-positive steps, numbetween != 2, ...). */
+int32_t jerk_plan_create(const jerk_plan_desc* desc, jerk_plan** out);
+int32_t jerk_plan_destroy(jerk_plan* plan);
+int32_t jerk_plan_info(const jerk_plan* plan, jerk_plan_info_t* out);
+int32_t jerk_plan_group(const jerk_plan* plan, int32_t g, jerk_group_info_t* out);
+/* Parameters of template t: zbar, w, half-width h_t, width group and slot in it. */
+int32_t jerk_plan_template(const jerk_plan* plan, int32_t t, double* zbar, double* w,
+                           int32_t* half_width, int32_t* group, int32_t* slot);
+/* Template indices of all groups, group by group (n_templates int32, host memory). */
+int32_t jerk_plan_members(const jerk_plan* plan, int32_t* out, int32_t count);
+/* Overrides one group's FFT segment length, templates per block and path before
+ * jerk_templates_build (used by the autotuner). Changes bank_bytes; EINVAL if out of range. */
+int32_t jerk_plan_set_group(jerk_plan* plan, int32_t g, int32_t seg_len,
+                            int32_t templates_per_block, int32_t path);
+
+/* ---- template bank (FP64 generation on the GPU) -------------------------- */
+/* Generates every template's taps in FP64 by composite Gauss-Legendre quadrature of R
+ * (16 nodes per panel, at most one phase cycle per panel) and derives the bank of each
+ * group's path: FP32 segment spectra for the FFT path, BF16 hi/lo or FP16 tap
+ * fragments for the MFMA path. d_bank: device buffer of at least bank_bytes.
+ * Asynchronous on stream. ENOMEM if bank_bytes is too small. */
+int32_t jerk_templates_build(jerk_plan* plan, void* d_bank, size_t bank_bytes, hipStream_t stream);
+
+/* ---- search ----------------------------------------------------------------- */
+/* Writes plane rows [t_begin, t_end) (all 2 nbins outputs each) of the spectrum d_spec
+ * (nbins complex64 values, any nbins >= 1) into d_plane, row t at d_plane + (t - t_begin) * ld,
+ * ld >= 2 nbins floats. Uses the bank built by jerk_templates_build for this plan.
+ * d_ws: workspace of at least workspace_bytes (may be NULL when that is 0).
+ * Asynchronous on stream. EINVAL for a bad range or stride. An empty range (t_begin == t_end)
+ * queues nothing and ignores the pointers. */
+int32_t jerk_search(const jerk_plan* plan, const void* d_bank, const void* d_spec, int64_t nbins,
+                    float* d_plane, int64_t ld, int32_t t_begin, int32_t t_end, void* d_ws,
+                    size_t ws_bytes, hipStream_t stream);
+
+/* As jerk_search, restricted to the templates of width group g (one kernel launch). Lets a
+ * caller time or schedule the groups separately; the union over all groups equals jerk_search. */
+int32_t jerk_search_group(const jerk_plan* plan, const void* d_bank, const void* d_spec, int64_t nbins,
+                          float* d_plane, int64_t ld, int32_t t_begin, int32_t t_end, int32_t g,
+                          hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JERK_H */

@@ -1,0 +1,165 @@
+"""MI355X (gfx950) Fourier-domain jerk search matched filter: Python binding.
+
+Thin wrapper over the C ABI in ``include/jerk.h`` (same names). It only
+marshals arguments: every step of the search runs in the HIP kernels of
+``libjerk.so``. PyTorch supplies device memory and streams; tensors are passed
+to the library as raw device pointers.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (JERK_EAGAIN, JERK_EINVAL, JERK_ENOMEM, JERK_EPENDING, JERK_OK, PATH_AUTO, PATH_FFT_FP32,
+                   PATH_GEMM_FP16, PATH_GEMM_SPLIT_BF16, PATH_NAMES, JerkError)
+
+__all__ = [
+    "Plan", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
+    "PATH_AUTO", "PATH_NAMES", "JERK_OK", "JERK_EINVAL", "JERK_ENOMEM", "JERK_EAGAIN", "JERK_EPENDING",
+]
+
+
+def load():
+    """Load the HIP library; raises ImportError if it is not built."""
+    return _lib.load()
+
+
+def version() -> str:
+    return _lib.load().jerk_version().decode()
+
+
+def _stream_ptr(stream) -> C.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+def _dev_ptr(t) -> C.c_void_p:
+    if t is None:
+        return C.c_void_p(0)
+    if not t.is_cuda:
+        raise ValueError("tensor must be in device memory")
+    return C.c_void_p(int(t.data_ptr()))
+
+
+class Plan:
+    """A search plan: lattice, half-widths, width groups and bank layout (host object).
+
+    Mirrors ``jerk_plan_create``; ``path`` is one of ``"fft"``, ``"split_bf16"``,
+    ``"fp16"``, ``"auto"`` or a ``PATH_*`` constant.
+    """
+
+    def __init__(self, nbins: int, zmax: float, wmax: float, dz: float = 2.0, dw: float = 20.0,
+                 path="fft", margin: int = 16, seg_len: int = 0, templates_per_block: int = 0,
+                 tap_quantum: int = 0, numbetween: int = 2):
+        lib = _lib.load()
+        if isinstance(path, str):
+            path = PATH_NAMES[path]
+        d = _lib.PlanDesc(nbins=nbins, zmax=zmax, wmax=wmax, dz=dz, dw=dw, numbetween=numbetween,
+                          margin_bins=margin, path=path, seg_len=seg_len,
+                          templates_per_block=templates_per_block, tap_quantum=tap_quantum, flags=0)
+        h = C.c_void_p()
+        _lib.check(lib.jerk_plan_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.desc = d
+
+    # -- host queries ---------------------------------------------------------
+    @property
+    def handle(self) -> C.c_void_p:
+        if self._h is None:
+            raise ValueError("plan is closed")
+        return self._h
+
+    def info(self) -> dict:
+        out = _lib.PlanInfo()
+        _lib.check(_lib.load().jerk_plan_info(self.handle, C.byref(out)))
+        return {f: getattr(out, f) for f, _ in out._fields_}
+
+    def group(self, g: int) -> dict:
+        out = _lib.GroupInfo()
+        _lib.check(_lib.load().jerk_plan_group(self.handle, g, C.byref(out)))
+        return {f: getattr(out, f) for f, _ in out._fields_}
+
+    def groups(self) -> list:
+        return [self.group(g) for g in range(self.info()["n_groups"])]
+
+    def template(self, t: int) -> tuple:
+        zb, w = C.c_double(), C.c_double()
+        h, g, s = C.c_int32(), C.c_int32(), C.c_int32()
+        _lib.check(_lib.load().jerk_plan_template(self.handle, t, C.byref(zb), C.byref(w), C.byref(h),
+                                                  C.byref(g), C.byref(s)))
+        return zb.value, w.value, h.value, g.value, s.value
+
+    def members(self) -> np.ndarray:
+        n = self.info()["n_templates"]
+        out = np.zeros(n, dtype=np.int32)
+        _lib.check(_lib.load().jerk_plan_members(self.handle, out.ctypes.data_as(C.POINTER(C.c_int32)), n))
+        return out
+
+    def set_group(self, g: int, seg_len: int, templates_per_block: int, path) -> None:
+        if isinstance(path, str):
+            path = PATH_NAMES[path]
+        _lib.check(_lib.load().jerk_plan_set_group(self.handle, g, seg_len, templates_per_block, path))
+
+    # -- device work ------------------------------------------------------------
+    def new_bank(self, device="cuda"):
+        import torch
+        return torch.empty(self.info()["bank_bytes"], dtype=torch.uint8, device=device)
+
+    def build_templates(self, bank, stream=None) -> None:
+        _lib.check(_lib.load().jerk_templates_build(self.handle, _dev_ptr(bank), bank.numel() * bank.element_size(),
+                                                    _stream_ptr(stream)))
+
+    def search(self, bank, spec, plane, t_begin: int = 0, t_end: int | None = None, ws=None,
+               stream=None) -> None:
+        """Enqueue ``jerk_search``: rows [t_begin, t_end) of ``spec``'s plane into ``plane``.
+
+        ``spec``: complex64 device tensor (n,). ``plane``: float32 device tensor
+        (rows, >= 2n) whose row stride is the plane's ``ld``.
+        """
+        import torch
+        if spec.dtype != torch.complex64 or spec.dim() != 1 or not spec.is_contiguous():
+            raise ValueError("spec must be a contiguous 1-D complex64 tensor")
+        if plane.dtype != torch.float32 or plane.dim() != 2 or plane.stride(1) != 1:
+            raise ValueError("plane must be a 2-D float32 tensor with unit column stride")
+        n = spec.shape[0]
+        if t_end is None:
+            t_end = self.info()["n_templates"]
+        if plane.shape[0] < t_end - t_begin or plane.shape[1] < 2 * n:
+            raise ValueError("plane too small for the requested rows")
+        ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
+        _lib.check(_lib.load().jerk_search(self.handle, _dev_ptr(bank), _dev_ptr(spec), n, _dev_ptr(plane),
+                                           plane.stride(0), t_begin, t_end, _dev_ptr(ws), ws_bytes,
+                                           _stream_ptr(stream)))
+
+    def search_group(self, bank, spec, plane, g: int, t_begin: int = 0, t_end: int | None = None,
+                     stream=None) -> None:
+        """Enqueue ``jerk_search_group``: like ``search`` for width group ``g`` only."""
+        n = spec.shape[0]
+        if t_end is None:
+            t_end = self.info()["n_templates"]
+        if plane.shape[0] < t_end - t_begin or plane.shape[1] < 2 * n or plane.stride(1) != 1:
+            raise ValueError("plane too small for the requested rows")
+        _lib.check(_lib.load().jerk_search_group(self.handle, _dev_ptr(bank), _dev_ptr(spec), n, _dev_ptr(plane),
+                                                 plane.stride(0), t_begin, t_end, g, _stream_ptr(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _lib.load().jerk_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,114 @@
+"""ctypes declarations of ``include/jerk.h`` (argument marshalling only).
+
+The shared library is loaded from this package's directory. There is no
+fallback: if ``libjerk.so`` is missing the import of the binding fails with a
+message saying how to build it.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjerk.so")
+
+JERK_OK = 0
+JERK_EINVAL = -1
+JERK_ENOMEM = -2
+JERK_EAGAIN = -3
+JERK_EPENDING = -4
+JERK_EHIP = -5
+JERK_EUNSUPPORTED = -6
+JERK_EINTERNAL = -7
+
+PATH_FFT_FP32 = 0
+PATH_GEMM_SPLIT_BF16 = 1
+PATH_GEMM_FP16 = 2
+PATH_AUTO = 3
+PATH_NAMES = {"fft": PATH_FFT_FP32, "split_bf16": PATH_GEMM_SPLIT_BF16, "fp16": PATH_GEMM_FP16,
+              "auto": PATH_AUTO}
+
+
+class PlanDesc(C.Structure):
+    _fields_ = [
+        ("nbins", C.c_int64),
+        ("zmax", C.c_double), ("wmax", C.c_double), ("dz", C.c_double), ("dw", C.c_double),
+        ("numbetween", C.c_int32), ("margin_bins", C.c_int32), ("path", C.c_int32),
+        ("seg_len", C.c_int32), ("templates_per_block", C.c_int32), ("tap_quantum", C.c_int32),
+        ("flags", C.c_uint32),
+    ]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [
+        ("n_z", C.c_int32), ("n_w", C.c_int32), ("n_templates", C.c_int32), ("n_groups", C.c_int32),
+        ("nbins", C.c_int64), ("n_r", C.c_int64),
+        ("max_taps", C.c_int32), ("path", C.c_int32),
+        ("bank_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t), ("plane_row_bytes", C.c_size_t),
+        ("taps_offset", C.c_size_t),
+    ]
+
+
+class GroupInfo(C.Structure):
+    _fields_ = [
+        ("taps", C.c_int32), ("seg_len", C.c_int32), ("templates_per_block", C.c_int32),
+        ("path", C.c_int32), ("n_members", C.c_int32), ("first_member", C.c_int32),
+        ("taps_offset", C.c_size_t),
+    ]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "jerk_status_str": (C.c_char_p, [C.c_int32]),
+    "jerk_last_error": (C.c_char_p, []),
+    "jerk_version": (C.c_char_p, []),
+    "jerk_plan_create": (C.c_int32, [C.POINTER(PlanDesc), C.POINTER(C.c_void_p)]),
+    "jerk_plan_destroy": (C.c_int32, [C.c_void_p]),
+    "jerk_plan_info": (C.c_int32, [C.c_void_p, C.POINTER(PlanInfo)]),
+    "jerk_plan_group": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(GroupInfo)]),
+    "jerk_plan_template": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "jerk_plan_members": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32]),
+    "jerk_plan_set_group": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "jerk_templates_build": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "jerk_search": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "jerk_search_group": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                      C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
+}
+
+_lib = None
+
+
+class JerkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{status_str(status)} ({status}): {msg}")
+        self.status = status
+
+
+def load() -> C.CDLL:
+    """Load ``libjerk.so`` (once). Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_1911_01353_amd.build` "
+                          "(the HIP library is required; there is no fallback)")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_str(status: int) -> str:
+    return load().jerk_status_str(status).decode()
+
+
+def check(status: int) -> None:
+    if status != JERK_OK:
+        msg = load().jerk_last_error().decode()
+        raise JerkError(status, msg)

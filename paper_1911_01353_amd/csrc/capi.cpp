@@ -1,0 +1,285 @@
+// C ABI entry points: argument checks, status codes and per-thread error text.
+// No C++ exception crosses this boundary.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "jerk_internal.h"
+
+namespace jerk {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+template <class F>
+int32_t guarded(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return JERK_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return JERK_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = std::string("internal error: ") + e.what();
+    return JERK_EINTERNAL;
+  } catch (...) {
+    g_last_error = "internal error";
+    return JERK_EINTERNAL;
+  }
+}
+
+void gen_twiddles(float2* out, int32_t n, hipStream_t stream);
+
+// Member sub-range [lo, hi) of group g whose templates lie in [t_begin, t_end).
+static void member_range(const Group& g, int32_t t_begin, int32_t t_end, int32_t* lo, int32_t* hi) {
+  *lo = (int32_t)(std::lower_bound(g.members.begin(), g.members.end(), t_begin) - g.members.begin());
+  *hi = (int32_t)(std::lower_bound(g.members.begin(), g.members.end(), t_end) - g.members.begin());
+}
+
+void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64_t nbins, float* d_plane,
+                    int64_t ld, int32_t t_begin, int32_t t_end, int32_t g_begin, int32_t g_end,
+                    hipStream_t stream) {
+  const char* bank = static_cast<const char*>(d_bank);
+  const int32_t* members = reinterpret_cast<const int32_t*>(bank + p.off_members);
+  for (int32_t gi = g_begin; gi < g_end; ++gi) {
+    const Group& g = p.groups[gi];
+    int32_t lo, hi;
+    member_range(g, t_begin, t_end, &lo, &hi);
+    if (lo >= hi) continue;
+    if (g.path == JERK_PATH_FFT_FP32) {
+      FftArgs a{};
+      a.spec = static_cast<const float2*>(d_spec);
+      a.nbins = nbins;
+      a.bank_fft = reinterpret_cast<const float2*>(bank + g.off_fft);
+      a.members = members + g.first_member;
+      a.m_begin = lo;
+      a.m_end = hi;
+      a.t_begin = t_begin;
+      a.plane = d_plane;
+      a.ld = ld;
+      a.taps = g.taps;
+      a.seg_len = g.seg_len;
+      a.tpb = g.tpb;
+      fft_correlate_launch(a, reinterpret_cast<const float2*>(bank + p.off_tw[tw_slot(g.seg_len)]), stream);
+    } else {
+      GemmArgs a{};
+      a.spec = static_cast<const float2*>(d_spec);
+      a.nbins = nbins;
+      a.bank_gemm = bank + g.off_gemm;
+      a.members = members + g.first_member;
+      a.m_begin = lo / 8 * 8;
+      a.m_end = hi;
+      a.t_begin = t_begin;
+      a.t_end = t_end;
+      a.plane = d_plane;
+      a.ld = ld;
+      a.taps = g.taps;
+      a.path = g.path;
+      gemm_correlate_launch(a, stream);
+    }
+  }
+}
+
+}  // namespace jerk
+
+using jerk::Error;
+using jerk::guarded;
+using jerk::require;
+
+extern "C" {
+
+const char* jerk_status_str(int32_t s) {
+  switch (s) {
+    case JERK_OK: return "JERK_OK";
+    case JERK_EINVAL: return "JERK_EINVAL";
+    case JERK_ENOMEM: return "JERK_ENOMEM";
+    case JERK_EAGAIN: return "JERK_EAGAIN";
+    case JERK_EPENDING: return "JERK_EPENDING";
+    case JERK_EHIP: return "JERK_EHIP";
+    case JERK_EUNSUPPORTED: return "JERK_EUNSUPPORTED";
+    case JERK_EINTERNAL: return "JERK_EINTERNAL";
+    default: return "JERK_UNKNOWN";
+  }
+}
+
+const char* jerk_last_error(void) { return jerk::g_last_error.c_str(); }
+
+const char* jerk_version(void) { return "jerk-mi355x 1.0 gfx950"; }
+
+int32_t jerk_plan_create(const jerk_plan_desc* desc, jerk_plan** out) {
+  return guarded([&] {
+    require(desc != nullptr && out != nullptr, JERK_EINVAL, "desc and out must not be NULL");
+    *out = nullptr;
+    jerk_plan* p = new jerk_plan();
+    try {
+      jerk::plan_build(p->p, *desc);
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    *out = p;
+  });
+}
+
+int32_t jerk_plan_destroy(jerk_plan* plan) {
+  return guarded([&] {
+    if (!plan) return;
+    if (plan->p.pinned_members) (void)hipHostFree(plan->p.pinned_members);
+    delete plan;
+  });
+}
+
+int32_t jerk_plan_info(const jerk_plan* plan, jerk_plan_info_t* out) {
+  return guarded([&] {
+    require(plan && out, JERK_EINVAL, "plan and out must not be NULL");
+    const jerk::Plan& p = plan->p;
+    std::memset(out, 0, sizeof(*out));
+    out->n_z = p.n_z;
+    out->n_w = p.n_w;
+    out->n_templates = p.T;
+    out->n_groups = (int32_t)p.groups.size();
+    out->nbins = p.desc.nbins;
+    out->n_r = 2 * p.desc.nbins;
+    out->max_taps = p.max_taps;
+    out->path = p.desc.path;
+    out->bank_bytes = p.bank_bytes;
+    out->workspace_bytes = 0;
+    out->plane_row_bytes = (size_t)(2 * p.desc.nbins) * sizeof(float);
+    out->taps_offset = p.groups.empty() ? 0 : p.groups[0].off_taps;
+  });
+}
+
+int32_t jerk_plan_group(const jerk_plan* plan, int32_t g, jerk_group_info_t* out) {
+  return guarded([&] {
+    require(plan && out, JERK_EINVAL, "plan and out must not be NULL");
+    require(g >= 0 && g < (int32_t)plan->p.groups.size(), JERK_EINVAL, "group index out of range");
+    const jerk::Group& G = plan->p.groups[g];
+    std::memset(out, 0, sizeof(*out));
+    out->taps = G.taps;
+    out->seg_len = G.seg_len;
+    out->templates_per_block = G.tpb;
+    out->path = G.path;
+    out->n_members = (int32_t)G.members.size();
+    out->first_member = G.first_member;
+    out->taps_offset = G.off_taps;
+  });
+}
+
+int32_t jerk_plan_template(const jerk_plan* plan, int32_t t, double* zbar, double* w, int32_t* half_width,
+                           int32_t* group, int32_t* slot) {
+  return guarded([&] {
+    require(plan != nullptr, JERK_EINVAL, "plan must not be NULL");
+    require(t >= 0 && t < plan->p.T, JERK_EINVAL, "template index out of range");
+    const jerk::Plan& p = plan->p;
+    if (zbar) *zbar = p.zbar[t];
+    if (w) *w = p.w[t];
+    if (half_width) *half_width = p.half[t];
+    if (group) *group = p.group_of[t];
+    if (slot) *slot = p.slot[t];
+  });
+}
+
+int32_t jerk_plan_members(const jerk_plan* plan, int32_t* out, int32_t count) {
+  return guarded([&] {
+    require(plan && out, JERK_EINVAL, "plan and out must not be NULL");
+    require(count >= plan->p.T, JERK_ENOMEM, "output holds fewer than n_templates entries");
+    int32_t k = 0;
+    for (const auto& g : plan->p.groups)
+      for (int32_t t : g.members) out[k++] = t;
+  });
+}
+
+int32_t jerk_plan_set_group(jerk_plan* plan, int32_t g, int32_t seg_len, int32_t templates_per_block,
+                            int32_t path) {
+  return guarded([&] {
+    require(plan != nullptr, JERK_EINVAL, "plan must not be NULL");
+    jerk::Plan& p = plan->p;
+    require(g >= 0 && g < (int32_t)p.groups.size(), JERK_EINVAL, "group index out of range");
+    jerk::Group& G = p.groups[g];
+    require(jerk::seg_len_supported(seg_len) && seg_len >= 2 * G.taps, JERK_EINVAL,
+            "seg_len must be 512..4096 (power of two) and at least twice the group's taps");
+    require(templates_per_block >= 1 && templates_per_block <= 64, JERK_EINVAL,
+            "templates_per_block must be in [1, 64]");
+    require(path == JERK_PATH_FFT_FP32 || path == JERK_PATH_GEMM_SPLIT_BF16 || path == JERK_PATH_GEMM_FP16,
+            JERK_EINVAL, "group path must be FFT_FP32, GEMM_SPLIT_BF16 or GEMM_FP16");
+    require(path == JERK_PATH_FFT_FP32 || G.taps <= 512, JERK_EUNSUPPORTED,
+            "MFMA paths support templates up to 512 taps");
+    G.seg_len = seg_len;
+    G.tpb = templates_per_block;
+    G.path = path;
+    jerk::plan_layout(p);
+  });
+}
+
+int32_t jerk_templates_build(jerk_plan* plan, void* d_bank, size_t bank_bytes, hipStream_t stream) {
+  return guarded([&] {
+    require(plan != nullptr && d_bank != nullptr, JERK_EINVAL, "plan and d_bank must not be NULL");
+    jerk::Plan& p = plan->p;
+    require(bank_bytes >= p.bank_bytes, JERK_ENOMEM, "bank buffer smaller than bank_bytes");
+    require(reinterpret_cast<uintptr_t>(d_bank) % 256 == 0, JERK_EINVAL, "bank must be 256-byte aligned");
+    if (!p.pinned_members) {
+      void* h = nullptr;
+      JERK_HIP_CHECK(hipHostMalloc(&h, sizeof(int32_t) * (size_t)p.T, hipHostMallocDefault));
+      p.pinned_members = static_cast<int32_t*>(h);
+      int32_t k = 0;
+      for (const auto& g : p.groups)
+        for (int32_t t : g.members) p.pinned_members[k++] = t;
+    }
+    char* bank = static_cast<char*>(d_bank);
+    JERK_HIP_CHECK(hipMemcpyAsync(bank + p.off_members, p.pinned_members, sizeof(int32_t) * (size_t)p.T,
+                                  hipMemcpyHostToDevice, stream));
+    for (int i = 0; i < 4; ++i)
+      jerk::gen_twiddles(reinterpret_cast<float2*>(bank + p.off_tw[i]), 512 << i, stream);
+    jerk::templates_build(p, d_bank, stream);
+  });
+}
+
+int32_t jerk_search(const jerk_plan* plan, const void* d_bank, const void* d_spec, int64_t nbins, float* d_plane,
+                    int64_t ld, int32_t t_begin, int32_t t_end, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  (void)d_ws;
+  (void)ws_bytes;
+  return guarded([&] {
+    require(plan != nullptr, JERK_EINVAL, "plan must not be NULL");
+    const jerk::Plan& p = plan->p;
+    require(0 <= t_begin && t_begin <= t_end && t_end <= p.T, JERK_EINVAL, "template range outside [0, n_templates]");
+    if (t_begin == t_end) return;  // empty range: nothing to do, pointers unused
+    require(d_bank && d_spec && d_plane, JERK_EINVAL, "bank, spectrum and plane must not be NULL");
+    require(nbins >= 1, JERK_EINVAL, "nbins must be >= 1");
+    require(ld >= 2 * nbins, JERK_EINVAL, "ld must be >= 2 * nbins");
+    require(ld % 2 == 0, JERK_EINVAL, "ld must be even (phase pairs are stored as float2)");
+    require(reinterpret_cast<uintptr_t>(d_plane) % 8 == 0 && reinterpret_cast<uintptr_t>(d_spec) % 8 == 0,
+            JERK_EINVAL, "spectrum and plane must be 8-byte aligned");
+    require(0 <= t_begin && t_begin <= t_end && t_end <= p.T, JERK_EINVAL, "template range outside [0, n_templates]");
+    jerk::search_enqueue(p, d_bank, d_spec, nbins, d_plane, ld, t_begin, t_end, 0, (int32_t)p.groups.size(), stream);
+  });
+}
+
+int32_t jerk_search_group(const jerk_plan* plan, const void* d_bank, const void* d_spec, int64_t nbins,
+                          float* d_plane, int64_t ld, int32_t t_begin, int32_t t_end, int32_t g,
+                          hipStream_t stream) {
+  return guarded([&] {
+    require(plan != nullptr, JERK_EINVAL, "plan must not be NULL");
+    const jerk::Plan& p = plan->p;
+    require(0 <= t_begin && t_begin <= t_end && t_end <= p.T, JERK_EINVAL, "template range outside [0, n_templates]");
+    require(g >= 0 && g < (int32_t)p.groups.size(), JERK_EINVAL, "group index out of range");
+    if (t_begin == t_end) return;
+    require(d_bank && d_spec && d_plane, JERK_EINVAL, "bank, spectrum and plane must not be NULL");
+    require(nbins >= 1, JERK_EINVAL, "nbins must be >= 1");
+    require(ld >= 2 * nbins && ld % 2 == 0, JERK_EINVAL, "ld must be even and >= 2 * nbins");
+    require(reinterpret_cast<uintptr_t>(d_plane) % 8 == 0 && reinterpret_cast<uintptr_t>(d_spec) % 8 == 0,
+            JERK_EINVAL, "spectrum and plane must be 8-byte aligned");
+    require(0 <= t_begin && t_begin <= t_end && t_end <= p.T, JERK_EINVAL, "template range outside [0, n_templates]");
+    require(g >= 0 && g < (int32_t)p.groups.size(), JERK_EINVAL, "group index out of range");
+    jerk::search_enqueue(p, d_bank, d_spec, nbins, d_plane, ld, t_begin, t_end, g, g + 1, stream);
+  });
+}
+
+}  // extern "C"

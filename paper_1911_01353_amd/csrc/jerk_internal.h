@@ -1,0 +1,116 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/jerk.h"
+
+namespace jerk {
+
+// Error carried to the C ABI boundary, where it becomes a status code.
+struct Error : std::runtime_error {
+  int32_t status;
+  Error(int32_t s, const std::string& msg) : std::runtime_error(msg), status(s) {}
+};
+
+inline void require(bool ok, int32_t status, const std::string& msg) {
+  if (!ok) throw Error(status, msg);
+}
+
+#define JERK_HIP_CHECK(expr)                                                              \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::jerk::Error(JERK_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+// Per-width-group data. All templates of a group use K = taps (zero-padded
+// beyond their own 2 h_t window) and one FFT segment length.
+struct Group {
+  int32_t taps = 0;        // K_g (multiple of the tap quantum)
+  int32_t seg_len = 0;     // S_g
+  int32_t tpb = 8;         // templates per workgroup (FFT path)
+  int32_t path = JERK_PATH_FFT_FP32;
+  std::vector<int32_t> members;  // template indices, ascending
+  int32_t first_member = 0;      // offset in the concatenated member table
+  // bank byte offsets
+  size_t off_taps = 0;   // complex128 [n][2][taps]
+  size_t off_fft = 0;    // complex64 [n][2][seg_len]    (FFT path)
+  size_t off_gemm = 0;   // tap fragments                (MFMA paths)
+  size_t gemm_bytes = 0;
+};
+
+struct Plan {
+  jerk_plan_desc desc{};
+  int32_t n_z = 0, n_w = 0, J = 0, T = 0;
+  std::vector<double> zbar, w;
+  std::vector<int32_t> half;      // h_t
+  std::vector<int32_t> group_of;  // t -> g
+  std::vector<int32_t> slot;      // t -> index in group
+  std::vector<Group> groups;
+  size_t off_members = 0;         // int32 [T] member table (group by group)
+  size_t off_tw[4] = {0, 0, 0, 0}; // complex64 exp(-2 pi i k / S), S = 512 << i
+  int32_t* pinned_members = nullptr;  // host copy (pinned) uploaded by templates_build
+  size_t bank_bytes = 0;
+  int32_t max_taps = 0;
+  // Gauss-Legendre rule on [-1, 1] used by the template generator.
+  double gl_x[16], gl_w[16];
+};
+
+// plan.cpp
+void plan_build(Plan& p, const jerk_plan_desc& d);
+void plan_layout(Plan& p);  // recompute bank offsets after a group change
+inline int tw_slot(int32_t seg_len) { return seg_len == 512 ? 0 : seg_len == 1024 ? 1 : seg_len == 2048 ? 2 : 3; }
+bool seg_len_supported(int32_t s);
+
+// templates.hip
+void templates_build(const Plan& p, void* d_bank, hipStream_t stream);
+
+// fft_correlate.hip: one width group, member range [m_begin, m_end) of the group.
+struct FftArgs {
+  const float2* spec;
+  int64_t nbins;
+  const float2* bank_fft;     // group's spectra, member 0 phase 0
+  const int32_t* members;     // group's member list (device)
+  int32_t m_begin, m_end;     // members to process
+  int32_t t_begin;            // plane row of template t is (t - t_begin)
+  float* plane;
+  int64_t ld;
+  int32_t taps, seg_len, tpb;
+};
+// twiddles: exp(-2 pi i k / seg_len), k < seg_len (complex64, device).
+void fft_correlate_launch(const FftArgs& a, const float2* twiddles, hipStream_t stream);
+
+// gemm_correlate.hip
+struct GemmArgs {
+  const float2* spec;
+  int64_t nbins;
+  const void* bank_gemm;      // group's fragments
+  const int32_t* members;
+  int32_t m_begin, m_end;     // m_begin a multiple of 8 (a fragment row block)
+  int32_t t_begin, t_end;     // only templates in [t_begin, t_end) are written
+  float* plane;
+  int64_t ld;
+  int32_t taps;
+  int32_t path;               // JERK_PATH_GEMM_SPLIT_BF16 or JERK_PATH_GEMM_FP16
+};
+void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream);
+size_t gemm_bank_bytes(int32_t n_members, int32_t taps, int32_t path);
+
+// Error-reporting state of the C ABI.
+void set_last_error(const std::string& msg);
+
+}  // namespace jerk
+
+struct jerk_plan {
+  jerk::Plan p;
+};

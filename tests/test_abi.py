@@ -1,0 +1,117 @@
+"""CPU tests of the C ABI: symbols, host-side plan logic and argument checks (no GPU calls)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1911_01353_amd as J
+from paper_1911_01353_amd import _lib
+from oracle.grid import Grid
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(jerk_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = J.load()
+    names = _declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding declares a signature for each of them
+    assert set(names) <= set(_lib.SIGNATURES)
+
+
+def test_status_strings_and_version():
+    assert _lib.status_str(0) == "JERK_OK"
+    assert _lib.status_str(-2) == "JERK_ENOMEM"
+    assert J.version().startswith("jerk-mi355x")
+
+
+@pytest.mark.parametrize("zmax,wmax", [(20, 60), (100, 300), (200, 600), (50, 150), (0, 0), (7, 45)])
+def test_plan_lattice_matches_oracle(zmax, wmax):
+    p = J.Plan(4096, zmax, wmax, 2.0, 20.0)
+    g = Grid(zmax, wmax, 2.0, 20.0)
+    info = p.info()
+    assert (info["n_z"], info["n_w"], info["n_templates"]) == (g.n_z, g.n_w, g.n_templates)
+    ts = range(g.n_templates) if g.n_templates < 500 else np.linspace(0, g.n_templates - 1, 400).astype(int)
+    for t in ts:
+        zb, w, h, grp, slot = p.template(int(t))
+        assert (zb, w, h) == g.params(int(t))
+    assert info["max_taps"] == 2 * int(g.half_widths().max())
+
+
+def test_groups_partition_templates_by_width():
+    p = J.Plan(1 << 20, 200, 600, 2.0, 20.0, path="auto")
+    members = p.members()
+    assert sorted(members.tolist()) == list(range(p.info()["n_templates"]))
+    prev = 0
+    for gi, g in enumerate(p.groups()):
+        assert g["taps"] % 16 == 0 and g["taps"] > prev
+        prev = g["taps"]
+        ms = members[g["first_member"]:g["first_member"] + g["n_members"]]
+        assert np.all(np.diff(ms) > 0)
+        for t in ms[:: max(1, len(ms) // 7)]:
+            zb, w, h, grp, slot = p.template(int(t))
+            assert grp == gi and g["taps"] - 16 < 2 * h <= g["taps"]
+        # AUTO: narrow groups on the MFMA path, wide ones on the FFT path
+        assert g["path"] == (J.PATH_GEMM_SPLIT_BF16 if g["taps"] <= 96 else J.PATH_FFT_FP32)
+
+
+def test_bank_layout_grows_with_overrides():
+    p = J.Plan(1 << 16, 20, 60, 2.0, 20.0, path="fft")
+    b0 = p.info()["bank_bytes"]
+    p.set_group(0, 4096, 4, "fft")
+    assert p.info()["bank_bytes"] > b0
+    g0 = p.group(0)
+    assert (g0["seg_len"], g0["templates_per_block"]) == (4096, 4)
+
+
+@pytest.mark.parametrize("kwargs,status", [
+    (dict(dz=0.0), J.JERK_EINVAL),
+    (dict(dw=-1.0), J.JERK_EINVAL),
+    (dict(numbetween=4), J.JERK_EINVAL),
+    (dict(seg_len=3000), J.JERK_EINVAL),
+    (dict(seg_len=512, zmax=200, wmax=600), J.JERK_EINVAL),  # segment too short for the widest group
+    (dict(margin=-1), J.JERK_EINVAL),
+    (dict(path=7), J.JERK_EINVAL),
+    (dict(path="split_bf16", zmax=400, wmax=1800), -6),   # wider than the MFMA kernels accept
+])
+def test_plan_argument_errors(kwargs, status):
+    args = dict(nbins=1024, zmax=20, wmax=60, dz=2.0, dw=20.0)
+    args.update(kwargs)
+    with pytest.raises(J.JerkError) as ei:
+        J.Plan(**args)
+    assert ei.value.status == status
+    assert J.load().jerk_last_error().decode()
+
+
+def test_search_argument_errors_are_synchronous():
+    """Bad arguments are rejected before anything touches a device."""
+    lib = J.load()
+    p = J.Plan(1024, 20, 60)
+    fake = C.c_void_p(0x100000)  # never dereferenced: validation fails first
+    null = C.c_void_p(0)
+    # ld too small
+    assert lib.jerk_search(p.handle, fake, fake, 1024, fake, 100, 0, 1, null, 0, null) == J.JERK_EINVAL
+    # template range outside the plan
+    assert lib.jerk_search(p.handle, fake, fake, 1024, fake, 2048, 0, 148, null, 0, null) == J.JERK_EINVAL
+    assert lib.jerk_search(p.handle, fake, fake, 1024, fake, 2048, 5, 4, null, 0, null) == J.JERK_EINVAL
+    # NULL pointers
+    assert lib.jerk_search(p.handle, null, fake, 1024, fake, 2048, 0, 1, null, 0, null) == J.JERK_EINVAL
+    # bank too small
+    assert lib.jerk_templates_build(p.handle, fake, 16, null) == J.JERK_ENOMEM
+    # NULL plan everywhere
+    assert lib.jerk_plan_info(None, None) == J.JERK_EINVAL

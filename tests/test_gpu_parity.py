@@ -1,0 +1,179 @@
+"""GPU parity: the HIP library against the FP64 oracle, element by element.
+
+Tolerances (floored relative power error, row-mean floor):
+  FP32 FFT path and split-BF16 MFMA path: max <= 1e-4;
+  FP16 MFMA path: max <= 1e-2 (one FP16 product: each operand rounded to 2^-12
+  relative, RMS power error ~4e-4, tail maxima over 10^7 points ~5e-3).
+Peak locations must match the oracle's exactly.
+"""
+
+import numpy as np
+import pytest
+
+import paper_1911_01353_amd as J
+import synth
+from oracle import Grid, correlate_row, error_summary, oracle_plane, peak_index, template_taps
+
+from gpu_helpers import bank_taps, build_bank, device, gpu_plane
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fft": 1e-4, "split_bf16": 1e-4, "auto": 1e-4, "fp16": 1e-2}
+
+
+@pytest.fixture(scope="module")
+def c1():
+    cfg = synth.CONFIGS["c1"]
+    spec = synth.make_spectrum(cfg)
+    grid = Grid(cfg.zmax, cfg.wmax, cfg.dz, cfg.dw)
+    ora = oracle_plane(spec, grid)
+    return cfg, spec, grid, ora
+
+
+def test_templates_fp64_match_oracle(c1):
+    cfg, spec, grid, _ = c1
+    device()
+    for zmax, wmax, sample in [(cfg.zmax, cfg.wmax, None), (300.0, 900.0, 12)]:
+        plan = J.Plan(spec.shape[0], zmax, wmax, 2.0, 20.0, path="fft")
+        g_or = Grid(zmax, wmax, 2.0, 20.0)
+        bank = build_bank(plan)
+        members = plan.members()
+        worst = 0.0
+        for gi, g in enumerate(plan.groups()):
+            taps = bank_taps(plan, bank, gi)
+            ms = members[g["first_member"]: g["first_member"] + g["n_members"]]
+            idx = range(len(ms)) if sample is None else np.unique(np.linspace(0, len(ms) - 1, 2).astype(int))
+            for k in idx:
+                t = int(ms[k])
+                zb, w, h = g_or.params(t)
+                hg = g["taps"] // 2
+                for phase in (0, 1):
+                    want = np.zeros(g["taps"], dtype=np.complex128)
+                    want[hg - h: hg + h] = template_taps(zb, w, h, phase)
+                    worst = max(worst, float(np.max(np.abs(taps[k, phase] - want))))
+        assert worst < 1e-12, (zmax, wmax, worst)
+
+
+@pytest.mark.parametrize("path", ["fft", "split_bf16", "fp16", "auto"])
+def test_full_plane_2e15_bins(c1, path):
+    cfg, spec, grid, ora = c1
+    device()
+    plan = J.Plan(spec.shape[0], cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
+    bank = build_bank(plan)
+    got = gpu_plane(plan, bank, spec)
+    assert not np.isnan(got).any(), "unwritten plane points"
+    s = error_summary(got, ora)
+    print(f"{path}: max {s['max']:.3e} rms {s['rms']:.3e}")
+    assert s["max"] <= TOL[path], s
+    assert peak_index(got) == peak_index(ora) == (102, 16013)
+
+
+@pytest.mark.parametrize("seg_len", [512, 1024, 2048, 4096])
+def test_fft_segment_length_invariance(c1, seg_len):
+    cfg, spec, grid, ora = c1
+    device()
+    plan = J.Plan(spec.shape[0], cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path="fft", seg_len=seg_len)
+    got = gpu_plane(plan, build_bank(plan), spec)
+    s = error_summary(got, ora)
+    assert s["max"] <= 1e-4, (seg_len, s)
+
+
+def test_fft_templates_per_block_is_bit_exact(c1):
+    cfg, spec, grid, _ = c1
+    device()
+    ref = None
+    for tpb in (1, 3, 8, 64):
+        plan = J.Plan(spec.shape[0], cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path="fft", templates_per_block=tpb)
+        got = gpu_plane(plan, build_bank(plan), spec)
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), tpb
+
+
+@pytest.mark.parametrize("path", ["fft", "split_bf16"])
+def test_template_slabs_match_full_plane(c1, path):
+    cfg, spec, grid, _ = c1
+    device()
+    plan = J.Plan(spec.shape[0], cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
+    bank = build_bank(plan)
+    full = gpu_plane(plan, bank, spec)
+    for t0, t1 in [(0, 1), (5, 29), (100, 147), (146, 147), (37, 37)]:
+        part = gpu_plane(plan, bank, spec, t0, t1, ld=2 * spec.shape[0] + 6)
+        assert np.array_equal(part.view(np.uint32), full[t0:t1].view(np.uint32)), (t0, t1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 37, 1000, 4099])
+@pytest.mark.parametrize("path", ["fft", "split_bf16", "fp16"])
+def test_ragged_and_tiny_spectra(n, path):
+    device()
+    rng = np.random.default_rng(n)
+    spec = ((rng.standard_normal(n) + 1j * rng.standard_normal(n)) / np.sqrt(2)).astype(np.complex64)
+    grid = Grid(4.0, 40.0, 2.0, 20.0)
+    plan = J.Plan(n, 4.0, 40.0, 2.0, 20.0, path=path)
+    got = gpu_plane(plan, build_bank(plan), spec)
+    ora = oracle_plane(spec, grid)
+    assert not np.isnan(got).any()
+    assert error_summary(got, ora)["max"] <= TOL[path]
+
+
+def test_single_template_grid():
+    """zmax = wmax = 0: one template, the plane is Fourier interpolation of |X|."""
+    device()
+    rng = np.random.default_rng(3)
+    n = 5000
+    spec = ((rng.standard_normal(n) + 1j * rng.standard_normal(n)) / np.sqrt(2)).astype(np.complex64)
+    for path in ("fft", "split_bf16"):
+        plan = J.Plan(n, 0.0, 0.0, 2.0, 20.0, path=path)
+        got = gpu_plane(plan, build_bank(plan), spec)
+        ora = oracle_plane(spec, Grid(0.0, 0.0, 2.0, 20.0))
+        assert error_summary(got, ora)["max"] <= 1e-4
+
+
+def test_2e22_bins_sampled_windows():
+    """Full-size 2^22-bin search (201 x 61 templates): sampled rows and windows against the oracle."""
+    import torch
+    device()
+    cfg = synth.CONFIGS["c2"]
+    spec = synth.make_spectrum(cfg)
+    n = spec.shape[0]
+    grid = Grid(cfg.zmax, cfg.wmax, cfg.dz, cfg.dw)
+    T = grid.n_templates
+    # templates: the four corners (widest), the centre, and the one nearest each injected tone
+    picks = {0, grid.n_z - 1, T - grid.n_z, T - 1, T // 2}
+    tone_windows = []
+    for tone in cfg.tones:
+        rbar = tone.r0 + tone.z0 / 2 + tone.w0 / 6
+        zbar = tone.z0 + tone.w0 / 2
+        i = int(round((zbar + cfg.zmax) / cfg.dz))
+        j = int(round(tone.w0 / cfg.dw)) + grid.J
+        picks.add(j * grid.n_z + i)
+        tone_windows.append(int(2 * rbar) - 300)
+    windows = [0, n - 300, 2 * n - 600] + tone_windows
+    # oracle windows: taps once per (template, phase), direct correlation per window
+    ora = {}
+    for t in sorted(picks):
+        zb, w, h = grid.params(t)
+        taps = [template_taps(zb, w, h, ph) for ph in (0, 1)]
+        for p0 in windows:
+            k_lo, k_hi = p0 // 2, (p0 + 600 + 1) // 2
+            vals = np.zeros(600)
+            for ph in (0, 1):
+                y = correlate_row(spec, taps[ph], h, k_lo, k_hi)
+                p = 2 * np.arange(k_lo, k_hi) + ph
+                keep = (p >= p0) & (p < p0 + 600)
+                vals[p[keep] - p0] = (y.real ** 2 + y.imag ** 2)[keep]
+            ora[(t, p0)] = vals
+    for path in ("fft", "auto"):
+        plan = J.Plan(n, cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
+        bank = build_bank(plan)
+        worst = 0.0
+        for t in sorted(picks):
+            row = gpu_plane(plan, bank, spec, t, t + 1)[0]
+            assert not np.isnan(row).any()
+            for p0 in windows:
+                worst = max(worst, error_summary(row[None, p0:p0 + 600], ora[(t, p0)][None, :])["max"])
+        del bank
+        torch.cuda.empty_cache()
+        print(f"2^22 bins {path}: worst sampled error {worst:.3e}")
+        assert worst <= 1e-4
