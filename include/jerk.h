@@ -152,6 +152,46 @@ int32_t jerk_search_group(const jerk_plan* plan, const void* d_bank, const void*
                           float* d_plane, int64_t ld, int32_t t_begin, int32_t t_end, int32_t g,
                           hipStream_t stream);
 
+/* ---- batched search: many spectra, one persistent launch -------------------- */
+typedef struct jerk_batch_item {
+  const void* spec;  /* device complex64 spectrum [nbins]                                 */
+  int64_t nbins;     /* >= 1; items may have different lengths                          */
+  float* plane;      /* device plane rows [t_begin, t_end) x 2 nbins (row stride ld), or NULL */
+  int64_t ld;        /* even, >= 2 nbins when plane is set                              */
+  uint64_t* peaks;   /* device peak keys [t_end - t_begin][keys_ld], or NULL (see below)  */
+  int64_t keys_ld;   /* >= jerk_batch_keys_per_row(plan, nbins) when peaks is set        */
+} jerk_batch_item;
+
+#define JERK_BATCH_GRAPH 1u /* capture the launch in a hipGraph on first use and replay it */
+
+/* Workspace bytes jerk_batch_search needs for up to `count` items. */
+size_t jerk_batch_workspace_bytes(const jerk_plan* plan, int32_t count);
+/* Peak keys written per plane row for a spectrum of nbins bins (one per FFT segment). A key
+ * is (float bits of the power << 32) | (0xFFFFFFFF - p): the largest key of a row is its
+ * peak power, ties going to the lowest r index p (jerk_peaks_reduce turns keys into peaks). */
+int64_t jerk_batch_keys_per_row(const jerk_plan* plan, int64_t nbins);
+/* Searches rows [t_begin, t_end) of every item in ONE persistent kernel launch: workgroups
+ * take (spectrum, width group, template block, segment) tiles from a device counter until
+ * all are done. All width groups must be on the FFT path with one segment length.
+ * Results equal jerk_search's bit for bit. With JERK_BATCH_GRAPH the launch is captured in
+ * a hipGraph the first time (per plan, workspace and device) and replayed afterwards; the
+ * job table is rewritten before every replay. Overlapping calls on one plan serialise on
+ * its staging buffer. Asynchronous on stream. */
+int32_t jerk_batch_search(jerk_plan* plan, const void* d_bank, const jerk_batch_item* items, int32_t count,
+                          int32_t t_begin, int32_t t_end, void* d_ws, size_t ws_bytes, uint32_t flags,
+                          hipStream_t stream);
+
+/* Peak of one plane row: its largest power and that power's plane index p (r = p / 2). */
+typedef struct jerk_peak {
+  float power;
+  uint32_t p;
+} jerk_peak;
+
+/* Reduces peak keys [rows][keys_ld] (first keys_per_row of each row) to one jerk_peak per row.
+ * Rows whose keys were all left 0 report power 0 and p = 0xFFFFFFFF. Asynchronous on stream. */
+int32_t jerk_peaks_reduce(const uint64_t* d_keys, int32_t rows, int64_t keys_per_row, int64_t keys_ld,
+                          jerk_peak* d_out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

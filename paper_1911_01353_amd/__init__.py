@@ -17,7 +17,7 @@ from ._lib import (JERK_EAGAIN, JERK_EINVAL, JERK_ENOMEM, JERK_EPENDING, JERK_OK
                    PATH_GEMM_FP16, PATH_GEMM_SPLIT_BF16, PATH_NAMES, JerkError)
 
 __all__ = [
-    "Plan", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
+    "Plan", "peaks_reduce", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
     "PATH_AUTO", "PATH_NAMES", "JERK_OK", "JERK_EINVAL", "JERK_ENOMEM", "JERK_EAGAIN", "JERK_EPENDING",
 ]
 
@@ -147,6 +147,35 @@ class Plan:
         _lib.check(_lib.load().jerk_search_group(self.handle, _dev_ptr(bank), _dev_ptr(spec), n, _dev_ptr(plane),
                                                  plane.stride(0), t_begin, t_end, g, _stream_ptr(stream)))
 
+    # -- batched search -----------------------------------------------------------
+    def batch_workspace_bytes(self, count: int) -> int:
+        return int(_lib.load().jerk_batch_workspace_bytes(self.handle, count))
+
+    def keys_per_row(self, nbins: int) -> int:
+        return int(_lib.load().jerk_batch_keys_per_row(self.handle, nbins))
+
+    def batch_search(self, bank, items, ws, t_begin: int = 0, t_end: int | None = None, graph: bool = False,
+                     stream=None) -> None:
+        """Enqueue ``jerk_batch_search`` over ``items``: (spec, plane or None, peak keys or None).
+
+        ``plane``: float32 (rows, >= 2n); ``keys``: uint64-sized (rows, >= keys_per_row(n))
+        tensor (torch.int64 storage, zero-filled by the caller).
+        """
+        if t_end is None:
+            t_end = self.info()["n_templates"]
+        arr = (_lib.BatchItem * max(1, len(items)))()
+        for i, (spec, plane, keys) in enumerate(items):
+            n = spec.shape[0]
+            arr[i].spec = _dev_ptr(spec).value
+            arr[i].nbins = n
+            arr[i].plane = _dev_ptr(plane).value if plane is not None else None
+            arr[i].ld = plane.stride(0) if plane is not None else 0
+            arr[i].peaks = _dev_ptr(keys).value if keys is not None else None
+            arr[i].keys_ld = keys.stride(0) if keys is not None else 0
+        _lib.check(_lib.load().jerk_batch_search(self.handle, _dev_ptr(bank), arr, len(items), t_begin, t_end,
+                                                 _dev_ptr(ws), ws.numel() * ws.element_size(),
+                                                 _lib.BATCH_GRAPH if graph else 0, _stream_ptr(stream)))
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
             _lib.load().jerk_plan_destroy(self._h)
@@ -163,3 +192,11 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def peaks_reduce(keys, keys_per_row: int, out, stream=None) -> None:
+    """Enqueue ``jerk_peaks_reduce``: keys (rows, ld) int64 tensor -> out (rows, 2) int32-sized tensor of
+    (power bits, p) pairs (view it as float32 / uint32)."""
+    rows = keys.shape[0]
+    _lib.check(_lib.load().jerk_peaks_reduce(_dev_ptr(keys), rows, keys_per_row, keys.stride(0), _dev_ptr(out),
+                                             _stream_ptr(stream)))

@@ -58,6 +58,19 @@ class GroupInfo(C.Structure):
     ]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [
+        ("spec", C.c_void_p), ("nbins", C.c_int64), ("plane", C.c_void_p), ("ld", C.c_int64),
+        ("peaks", C.c_void_p), ("keys_ld", C.c_int64),
+    ]
+
+
+class Peak(C.Structure):
+    _fields_ = [("power", C.c_float), ("p", C.c_uint32)]
+
+
+BATCH_GRAPH = 1
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "jerk_status_str": (C.c_char_p, [C.c_int32]),
@@ -76,6 +89,11 @@ SIGNATURES = {
                                 C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "jerk_search_group": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                       C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
+    "jerk_batch_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int32]),
+    "jerk_batch_keys_per_row": (C.c_int64, [C.c_void_p, C.c_int64]),
+    "jerk_batch_search": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(BatchItem), C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_void_p, C.c_size_t, C.c_uint32, C.c_void_p]),
+    "jerk_peaks_reduce": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
 }
 
 _lib = None

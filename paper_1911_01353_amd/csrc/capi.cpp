@@ -55,20 +55,19 @@ void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64
     member_range(g, t_begin, t_end, &lo, &hi);
     if (lo >= hi) continue;
     if (g.path == JERK_PATH_FFT_FP32) {
-      FftArgs a{};
-      a.spec = static_cast<const float2*>(d_spec);
-      a.nbins = nbins;
-      a.bank_fft = reinterpret_cast<const float2*>(bank + g.off_fft);
-      a.members = members + g.first_member;
-      a.m_begin = lo;
-      a.m_end = hi;
-      a.t_begin = t_begin;
-      a.plane = d_plane;
-      a.ld = ld;
-      a.taps = g.taps;
-      a.seg_len = g.seg_len;
-      a.tpb = g.tpb;
-      fft_correlate_launch(a, reinterpret_cast<const float2*>(bank + p.off_tw[tw_slot(g.seg_len)]), stream);
+      FftJob j{};
+      j.spec = static_cast<const float2*>(d_spec);
+      j.nbins = nbins;
+      j.bank_fft = reinterpret_cast<const float2*>(bank + g.off_fft);
+      j.members = members + g.first_member;
+      j.m_begin = lo;
+      j.m_end = hi;
+      j.t_begin = t_begin;
+      j.plane = d_plane;
+      j.ld = ld;
+      j.taps = g.taps;
+      j.tpb = g.tpb;
+      fft_correlate_launch(j, g.seg_len, reinterpret_cast<const float2*>(bank + p.off_tw[tw_slot(g.seg_len)]), stream);
     } else {
       GemmArgs a{};
       a.spec = static_cast<const float2*>(d_spec);
@@ -133,6 +132,7 @@ int32_t jerk_plan_destroy(jerk_plan* plan) {
   return guarded([&] {
     if (!plan) return;
     if (plan->p.pinned_members) (void)hipHostFree(plan->p.pinned_members);
+    jerk::batch_ctx_free(plan->p.batch);
     delete plan;
   });
 }
@@ -279,6 +279,35 @@ int32_t jerk_search_group(const jerk_plan* plan, const void* d_bank, const void*
     require(0 <= t_begin && t_begin <= t_end && t_end <= p.T, JERK_EINVAL, "template range outside [0, n_templates]");
     require(g >= 0 && g < (int32_t)p.groups.size(), JERK_EINVAL, "group index out of range");
     jerk::search_enqueue(p, d_bank, d_spec, nbins, d_plane, ld, t_begin, t_end, g, g + 1, stream);
+  });
+}
+
+size_t jerk_batch_workspace_bytes(const jerk_plan* plan, int32_t count) {
+  if (!plan || count < 0) return 0;
+  return jerk::batch_workspace_bytes(plan->p, count);
+}
+
+int64_t jerk_batch_keys_per_row(const jerk_plan* plan, int64_t nbins) {
+  if (!plan || nbins < 1) return 0;
+  return jerk::batch_keys_per_row(plan->p, nbins);
+}
+
+int32_t jerk_batch_search(jerk_plan* plan, const void* d_bank, const jerk_batch_item* items, int32_t count,
+                          int32_t t_begin, int32_t t_end, void* d_ws, size_t ws_bytes, uint32_t flags,
+                          hipStream_t stream) {
+  return guarded([&] {
+    require(plan != nullptr, JERK_EINVAL, "plan must not be NULL");
+    jerk::batch_search(plan->p, d_bank, items, count, t_begin, t_end, d_ws, ws_bytes, flags, stream);
+  });
+}
+
+int32_t jerk_peaks_reduce(const uint64_t* d_keys, int32_t rows, int64_t keys_per_row, int64_t keys_ld,
+                          jerk_peak* d_out, hipStream_t stream) {
+  return guarded([&] {
+    require(rows >= 0 && keys_per_row >= 1 && keys_ld >= keys_per_row, JERK_EINVAL, "bad key layout");
+    if (rows == 0) return;
+    require(d_keys && d_out, JERK_EINVAL, "keys and output must not be NULL");
+    jerk::peaks_reduce(d_keys, rows, keys_per_row, keys_ld, d_out, stream);
   });
 }
 

@@ -18,6 +18,8 @@
 // stays in registers between the forward transform, the template multiply and
 // the inverse transform. One workgroup handles one segment and a block of
 // templates; the forward FFT of the segment is done once per workgroup.
+#include <algorithm>
+
 #include "jerk_internal.h"
 
 namespace jerk {
@@ -39,22 +41,43 @@ __device__ constexpr float kC16[8] = {1.0f, 0.92387953251128674f, 0.707106781186
 __device__ constexpr float kS16[8] = {0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f,
                                       1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f};
 
-// v * W_R^k with W_R = exp(-+2 pi i / R) (minus for the forward transform).
+// Radix-2 butterfly with a constant twiddle W = W_R^k = exp(-+2 pi i k / R)
+// (minus for the forward transform): x = e + W o, y = e - W o. General
+// twiddles use fused multiply-adds and y = 2e - x, six instructions instead of
+// eight; multiplications by 1 and -+i are free.
 template <int R, bool INV>
-__device__ __forceinline__ float2 twiddle_const(int k, float2 v) {
+__device__ __forceinline__ void butterfly(int k, float2 e, float2 o, float2& x, float2& y) {
   const int m = k * (16 / R);  // angle 2 pi m / 16
-  if (m == 0) return v;
-  if (m == 4) return INV ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
-  if (m == 2) {
-    const float c = 0.70710678118654752f;
-    return INV ? make_float2(c * (v.x - v.y), c * (v.x + v.y)) : make_float2(c * (v.x + v.y), c * (v.y - v.x));
+  if (m == 0) {
+    x = cadd(e, o);
+    y = csub(e, o);
+    return;
   }
-  if (m == 6) {
-    const float c = 0.70710678118654752f;
-    return INV ? make_float2(-c * (v.x + v.y), c * (v.x - v.y)) : make_float2(c * (v.y - v.x), -c * (v.x + v.y));
+  if (m == 4) {  // W = -i (forward) or +i (inverse)
+    const float2 t = INV ? make_float2(-o.y, o.x) : make_float2(o.y, -o.x);
+    x = cadd(e, t);
+    y = csub(e, t);
+    return;
   }
-  const float c = kC16[m], s = INV ? kS16[m] : -kS16[m];
-  return make_float2(fmaf(v.x, c, -v.y * s), fmaf(v.x, s, v.y * c));
+  float2 r;
+  if (m == 2 || m == 6) {
+    // W = (+-1 -+ i) / sqrt(2): W o = c (u, v) with u, v sums of o's parts
+    const float c = 0.70710678118654752f;
+    float u, v;
+    if (m == 2) {
+      u = INV ? o.x - o.y : o.x + o.y;
+      v = INV ? o.x + o.y : o.y - o.x;
+    } else {
+      u = INV ? -(o.x + o.y) : o.y - o.x;
+      v = INV ? o.x - o.y : -(o.x + o.y);
+    }
+    r = make_float2(fmaf(c, u, e.x), fmaf(c, v, e.y));
+  } else {
+    const float c = kC16[m], sn = INV ? kS16[m] : -kS16[m];
+    r = make_float2(fmaf(c, o.x, fmaf(-sn, o.y, e.x)), fmaf(sn, o.x, fmaf(c, o.y, e.y)));
+  }
+  x = r;
+  y = make_float2(fmaf(2.0f, e.x, -r.x), fmaf(2.0f, e.y, -r.y));
 }
 
 // In-register DFT of size R (power of two <= 16) by radix-2 decimation in time.
@@ -70,11 +93,7 @@ struct Dft {
     Dft<R / 2, INV>::run(e);
     Dft<R / 2, INV>::run(o);
 #pragma unroll
-    for (int k = 0; k < R / 2; ++k) {
-      const float2 t = twiddle_const<R, INV>(k, o[k]);
-      x[k] = cadd(e[k], t);
-      x[k + R / 2] = csub(e[k], t);
-    }
+    for (int k = 0; k < R / 2; ++k) butterfly<R, INV>(k, e[k], o[k], x[k], x[k + R / 2]);
   }
 };
 template <bool INV>
@@ -127,18 +146,40 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, const
   }
 }
 
+// Largest key of the lanes of a workgroup (TPB threads); returned to every thread.
+template <int TPB>
+__device__ __forceinline__ uint64_t block_max_key(uint64_t k, uint64_t* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint64_t o = __shfl_xor(k, off, 64);
+    k = o > k ? o : k;
+  }
+  if constexpr (TPB > 64) {
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[wave] = k;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < TPB / 64; ++w) k = red[w] > k ? red[w] : k;
+    __syncthreads();
+  }
+  return k;
+}
+
+// Reduction key of a power at plane index p: larger power wins, then lower p.
+__device__ __forceinline__ uint64_t peak_key(float power, int64_t p) {
+  return ((uint64_t)__float_as_uint(power) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)p);
+}
+
+// One tile: segment `seg` of job `j` against template block `tb` (up to j.tpb
+// templates of the job's member range). Writes the plane rows and/or the
+// per-(row, segment) peak keys.
 template <int S, int E, int R1, int R2, int R3>
-__global__ void __launch_bounds__(S / E) fft_correlate_kernel(FftArgs a, const float2* __restrict__ tw) {
+__device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int tb, float2* lds, uint64_t* red,
+                                         const float2* __restrict__ tw) {
   constexpr int TPB = S / E;
-  static_assert(R1 * R2 * R3 == S, "radices must multiply to S");
-  __shared__ float2 lds[S + S / 16];
   const int tid = threadIdx.x;
-  const int K = a.taps;
+  const int K = j.taps;
   const int U = S - K + 1;
-  const int64_t n_seg = (a.nbins + U - 1) / U;
-  const int64_t blk = blockIdx.x;
-  const int64_t seg = blk % n_seg;
-  const int tb = (int)(blk / n_seg);
   const int64_t base = seg * U - (K / 2 - 1);
 
   // ---- forward FFT of the segment (radices R1, R2, R3) ----
@@ -151,7 +192,7 @@ __global__ void __launch_bounds__(S / E) fft_correlate_kernel(FftArgs a, const f
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
         const int64_t k = base + b + r * (S / R1);
-        v[m * R1 + r] = (k >= 0 && k < a.nbins) ? a.spec[k] : make_float2(0.f, 0.f);
+        v[m * R1 + r] = (k >= 0 && k < j.nbins) ? j.spec[k] : make_float2(0.f, 0.f);
       }
     }
   }
@@ -163,20 +204,22 @@ __global__ void __launch_bounds__(S / E) fft_correlate_kernel(FftArgs a, const f
   for (int e = 0; e < E; ++e) F[e] = v[e];
 
   // ---- template loop ----
-  const int m0 = a.m_begin + tb * a.tpb;
-  const int m1 = min(m0 + a.tpb, a.m_end);
+  const int m0 = j.m_begin + tb * j.tpb;
+  const int m1 = min(m0 + j.tpb, j.m_end);
+  // lags kept by this segment: lag < U and k0 = seg U + lag < nbins
+  const int lag_lim = (int)min((int64_t)U, j.nbins - seg * U);
   for (int mm = m0; mm < m1; ++mm) {
-    const int t = a.members[mm];
-    float* row = a.plane + (int64_t)(t - a.t_begin) * a.ld;
+    const int t = j.members[mm];
+    const int64_t row = t - j.t_begin;
     float P0[E];
 #pragma unroll
     for (int phase = 0; phase < 2; ++phase) {
-      const float2* H = a.bank_fft + ((int64_t)mm * 2 + phase) * S;
+      const float2* __restrict__ H = j.bank_fft + ((int64_t)mm * 2 + phase) * S;
       {
         constexpr int M = E / R3;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-          const int b = tid + m * TPB;
+          const unsigned b = tid + m * TPB;
 #pragma unroll
           for (int k = 0; k < R3; ++k) v[m * R3 + k] = cmul(F[m * R3 + k], H[b + k * (S / R3)]);
         }
@@ -190,52 +233,167 @@ __global__ void __launch_bounds__(S / E) fft_correlate_kernel(FftArgs a, const f
         for (int e = 0; e < E; ++e) P0[e] = fmaf(v[e].x, v[e].x, v[e].y * v[e].y);
       } else {
         constexpr int M = E / R1;
+        uint64_t best = 0;
+        // uniform row base; lanes add 32-bit offsets
+        float2* __restrict__ out2 =
+            j.plane ? reinterpret_cast<float2*>(j.plane + row * j.ld) + seg * U : nullptr;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
           const int b = tid + m * TPB;
 #pragma unroll
           for (int k = 0; k < R1; ++k) {
             const int lag = b + k * (S / R1);
-            const int64_t k0 = seg * U + lag;
-            if (lag < U && k0 < a.nbins) {
+            if (lag < lag_lim) {
               const float2 vv = v[m * R1 + k];
+              const float p0 = P0[m * R1 + k];
               const float p1 = fmaf(vv.x, vv.x, vv.y * vv.y);
-              *reinterpret_cast<float2*>(row + 2 * k0) = make_float2(P0[m * R1 + k], p1);
+              if (out2) out2[(unsigned)lag] = make_float2(p0, p1);
+              if (j.row_max) {
+                const int64_t p = 2 * (seg * U + lag);
+                const uint64_t k0 = peak_key(p0, p), k1 = peak_key(p1, p + 1);
+                const uint64_t kk = k1 > k0 ? k1 : k0;
+                best = kk > best ? kk : best;
+              }
             }
           }
+        }
+        if (j.row_max) {
+          best = block_max_key<TPB>(best, red);
+          if (tid == 0) j.row_max[row * j.rmax_ld + seg] = best;
         }
       }
     }
   }
 }
 
+// One job, one workgroup per tile: blockIdx = tb * n_seg + seg.
+template <int S, int E, int R1, int R2, int R3>
+__global__ void __launch_bounds__(S / E) fft_correlate_kernel(FftJob j, const float2* __restrict__ tw) {
+  static_assert(R1 * R2 * R3 == S, "radices must multiply to S");
+  __shared__ float2 lds[S + S / 16];
+  __shared__ uint64_t red[4];
+  const int64_t blk = blockIdx.x;
+  fft_tile<S, E, R1, R2, R3>(j, blk % j.n_seg, (int)(blk / j.n_seg), lds, red, tw);
+}
+
+// Persistent launch over a job table: every workgroup takes tiles from a
+// device counter until all tiles of all jobs are done (every workgroup
+// reaches the exit test). Tile i belongs to the job whose [tile_begin,
+// next tile_begin) holds it; within a job, tile = tb * n_seg + seg.
+template <int S, int E, int R1, int R2, int R3>
+__global__ void __launch_bounds__(S / E) fft_persistent_kernel(const FftJob* __restrict__ jobs,
+                                                               BatchHeader* __restrict__ hdr,
+                                                               const float2* __restrict__ tw) {
+  __shared__ float2 lds[S + S / 16];
+  __shared__ uint64_t red[4];
+  __shared__ int64_t s_tile;
+  const int64_t total = hdr->total_tiles;
+  const int n_jobs = hdr->n_jobs;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(&hdr->counter, 1ull);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    __syncthreads();
+    if (tile >= total) break;
+    int lo = 0, hi = n_jobs - 1;  // last job with tile_begin <= tile
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].tile_begin <= tile) lo = mid;
+      else hi = mid - 1;
+    }
+    const FftJob& j = jobs[lo];
+    const int64_t local = tile - j.tile_begin;
+    fft_tile<S, E, R1, R2, R3>(j, local % j.n_seg, (int)(local / j.n_seg), lds, red, tw);
+  }
+}
+
+__global__ void batch_reset_kernel(BatchHeader* hdr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->counter = 0ull;
+}
+
 }  // namespace
 
-void fft_correlate_launch(const FftArgs& a, const float2* twiddles, hipStream_t stream) {
-  const int n_members = a.m_end - a.m_begin;
-  if (n_members <= 0 || a.nbins <= 0) return;
-  const int U = a.seg_len - a.taps + 1;
+int64_t fft_job_tiles(FftJob& j, int32_t seg_len) {
+  const int U = seg_len - j.taps + 1;
   require(U >= 1, JERK_EINTERNAL, "segment shorter than the template");
-  const int64_t n_seg = (a.nbins + U - 1) / U;
-  const int64_t n_tb = (n_members + a.tpb - 1) / a.tpb;
-  const int64_t blocks = n_seg * n_tb;
+  j.n_seg = (j.nbins + U - 1) / U;
+  const int64_t n_tb = (j.m_end - j.m_begin + j.tpb - 1) / j.tpb;
+  return j.n_seg * n_tb;
+}
+
+void fft_correlate_launch(FftJob j, int32_t seg_len, const float2* twiddles, hipStream_t stream) {
+  if (j.m_end <= j.m_begin || j.nbins <= 0) return;
+  const int64_t blocks = fft_job_tiles(j, seg_len);
   require(blocks < (1ll << 31), JERK_EINVAL, "search too large for one launch; split the template range");
-  switch (a.seg_len) {
+  switch (seg_len) {
     case 4096:
-      hipLaunchKernelGGL((fft_correlate_kernel<4096, 16, 16, 16, 16>), dim3((unsigned)blocks), dim3(256), 0,
-                         stream, a, twiddles);
+      hipLaunchKernelGGL((fft_correlate_kernel<4096, 16, 16, 16, 16>), dim3((unsigned)blocks), dim3(256), 0, stream, j,
+                         twiddles);
       break;
     case 2048:
-      hipLaunchKernelGGL((fft_correlate_kernel<2048, 16, 8, 16, 16>), dim3((unsigned)blocks), dim3(128), 0,
-                         stream, a, twiddles);
+      hipLaunchKernelGGL((fft_correlate_kernel<2048, 16, 8, 16, 16>), dim3((unsigned)blocks), dim3(128), 0, stream, j,
+                         twiddles);
       break;
     case 1024:
-      hipLaunchKernelGGL((fft_correlate_kernel<1024, 16, 4, 16, 16>), dim3((unsigned)blocks), dim3(64), 0,
-                         stream, a, twiddles);
+      hipLaunchKernelGGL((fft_correlate_kernel<1024, 16, 4, 16, 16>), dim3((unsigned)blocks), dim3(64), 0, stream, j,
+                         twiddles);
       break;
     case 512:
-      hipLaunchKernelGGL((fft_correlate_kernel<512, 8, 8, 8, 8>), dim3((unsigned)blocks), dim3(64), 0, stream,
-                         a, twiddles);
+      hipLaunchKernelGGL((fft_correlate_kernel<512, 8, 8, 8, 8>), dim3((unsigned)blocks), dim3(64), 0, stream, j,
+                         twiddles);
+      break;
+    default:
+      throw Error(JERK_EINTERNAL, "unsupported segment length");
+  }
+  JERK_HIP_CHECK(hipGetLastError());
+}
+
+int32_t fft_persistent_grid(int32_t seg_len) {
+  int dev = 0, cus = 0, per_cu = 0;
+  JERK_HIP_CHECK(hipGetDevice(&dev));
+  JERK_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  switch (seg_len) {
+    case 4096:
+      JERK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(fft_persistent_kernel<4096, 16, 16, 16, 16>), 256, 0));
+      break;
+    case 2048:
+      JERK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(fft_persistent_kernel<2048, 16, 8, 16, 16>), 128, 0));
+      break;
+    case 1024:
+      JERK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(fft_persistent_kernel<1024, 16, 4, 16, 16>), 64, 0));
+      break;
+    case 512:
+      JERK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(fft_persistent_kernel<512, 8, 8, 8, 8>), 64, 0));
+      break;
+    default:
+      throw Error(JERK_EINTERNAL, "unsupported segment length");
+  }
+  return std::max(1, cus) * std::max(1, per_cu);
+}
+
+void fft_persistent_launch(const FftJob* d_jobs, BatchHeader* d_hdr, int32_t seg_len, const float2* twiddles,
+                           int32_t grid, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, d_hdr);
+  switch (seg_len) {
+    case 4096:
+      hipLaunchKernelGGL((fft_persistent_kernel<4096, 16, 16, 16, 16>), dim3(grid), dim3(256), 0, stream, d_jobs,
+                         d_hdr, twiddles);
+      break;
+    case 2048:
+      hipLaunchKernelGGL((fft_persistent_kernel<2048, 16, 8, 16, 16>), dim3(grid), dim3(128), 0, stream, d_jobs,
+                         d_hdr, twiddles);
+      break;
+    case 1024:
+      hipLaunchKernelGGL((fft_persistent_kernel<1024, 16, 4, 16, 16>), dim3(grid), dim3(64), 0, stream, d_jobs,
+                         d_hdr, twiddles);
+      break;
+    case 512:
+      hipLaunchKernelGGL((fft_persistent_kernel<512, 8, 8, 8, 8>), dim3(grid), dim3(64), 0, stream, d_jobs, d_hdr,
+                         twiddles);
       break;
     default:
       throw Error(JERK_EINTERNAL, "unsupported segment length");

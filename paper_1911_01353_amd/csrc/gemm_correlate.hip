@@ -30,10 +30,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kWaves = 4;          // waves per workgroup
-constexpr int kColTiles = 4;       // 32-column tiles per window
-constexpr int kWin = 32 * kColTiles;  // outputs per window
-constexpr int kKsChunk = 4;        // k-steps of tap fragments held in registers at once
+constexpr int kFragKsPad = 8;  // spare row blocks at the end of a group's fragments (see gemm_bank_bytes)
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
@@ -46,110 +43,140 @@ __device__ __forceinline__ uint16_t f16_bits(float x) {
   return __builtin_bit_cast(uint16_t, h);
 }
 
-// Window stride (elements) of one shifted copy: 64 m + 8, so that the eight
-// copies start 16 bytes apart modulo 128 bytes (distinct LDS banks for the
-// eight lanes of a ds_read_b128 group).
-__host__ __device__ constexpr int win_stride(int taps) { return ((kWin + taps + 8 + 63) / 64) * 64 + 8; }
+// LDS window of one wave: for each part (re_hi, im_hi, re_lo, im_lo; FP16: re, im)
+// two copies of the window, copy s holding element x + s at element index x, so
+// that any 8 consecutive elements starting at x are 4 aligned 32-bit words of
+// copy (x mod 2). Copy stride in words is 32 m + 16: the two copies of a part
+// start 16 banks apart.
+__host__ __device__ constexpr int win_words(int cols, int taps) {
+  return ((cols + taps + 8) / 2 + 15) / 32 * 32 + 16;
+}
 
-template <bool SPLIT>
-__host__ __device__ constexpr int n_parts() { return SPLIT ? 4 : 2; }  // (r_hi, i_hi, r_lo, i_lo) or (r, i)
+template <int CT>
+__host__ __device__ constexpr int window_cols() { return 32 * CT; }
 
-// Workgroup: kWaves waves, wave wv owns row blocks rb0 + wv*RB .. + RB-1 (8
-// templates each) and every column of the window.
-template <int RB, bool SPLIT>
-__global__ void __launch_bounds__(64 * kWaves) gemm_correlate_kernel(GemmArgs a, int64_t windows_per_wg,
-                                                                      int64_t n_colchunks) {
-  extern __shared__ uint16_t lds[];  // [parts][8 shifts][stride]
+// One wave per workgroup. The wave owns RB row blocks (8 templates each) of the
+// group and a run of consecutive windows of 32*CT outputs. Tap fragments for up
+// to KC k-steps stay in registers; the spectrum window is double-buffered in
+// LDS and the next window's loads are issued before the current window's MFMAs.
+template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT>
+__global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64_t windows_per_wg, int64_t n_colchunks) {
+  extern __shared__ uint32_t lds32[];
+  constexpr int P = SPLIT ? 2 : 1;        // parts of each operand (hi, lo)
+  constexpr int NPART = 2 * P;            // LDS part arrays (re/im x hi/lo)
+  constexpr int COLS = window_cols<CT>();
   const int K = a.taps;
   const int hg = K / 2;
-  const int KS = 2 * K / 16;        // k-steps of the real-expanded contraction
-  const int ksr = K / 16;           // k-steps over the real parts
-  const int stride = win_stride(K);
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int KS = 2 * K / 16;   // k-steps of the real-expanded contraction
+  const int ksr = K / 16;      // k-steps over the real parts
+  const int WW = win_words(COLS, K);
+  const int buf_words = NPART * 2 * WW;
+  const int lane = threadIdx.x;
   const int64_t cc = blockIdx.x % n_colchunks;
   const int tblk = (int)(blockIdx.x / n_colchunks);
   const int n_members = a.m_end - a.m_begin;
-  const int rb_first = (tblk * kWaves + wv) * RB;  // row block index within [m_begin, m_end) / 8
-  constexpr int P = SPLIT ? 2 : 1;  // parts of the tap operand
-
-  const uint16_t* frag = static_cast<const uint16_t*>(a.bank_gemm);
-  // Fragment (rb, ks, part) of the group: 64 lanes x 8 values.
-  auto frag_ptr = [&](int rb_global, int ks, int part) {
-    return frag + ((((int64_t)rb_global * KS + ks) * P + part) * 64 + lane) * 8;
+  const int rb0 = a.m_begin / 8 + tblk * RB;  // first row block (group-relative)
+  const uint16_t* __restrict__ frag = static_cast<const uint16_t*>(a.bank_gemm);
+  auto frag_ptr = [&](int rb, int ks, int part) {
+    return reinterpret_cast<const uint4*>(frag + ((((int64_t)rb * KS + ks) * P + part) * 64 + lane) * 8);
   };
-  const int rb_base_global = a.m_begin / 8;  // m_begin is a multiple of 8
 
-  for (int64_t wi = 0; wi < windows_per_wg; ++wi) {
-    const int64_t win = cc * windows_per_wg + wi;
-    const int64_t col0 = win * kWin;  // first output k0 of the window
-    if (col0 >= a.nbins) break;
-    // ---- fill the LDS window: position x holds bin col0 - hg + 1 + x + shift ----
-    const int64_t bin0 = col0 - hg + 1;
-    const int npos = kWin + K + 8;
-    for (int x = threadIdx.x; x < npos; x += 64 * kWaves) {
+  const int64_t win_first = cc * windows_per_wg;
+  const int64_t n_win_total = (a.nbins + COLS - 1) / COLS;
+  const int64_t win_last = min(win_first + windows_per_wg, n_win_total);
+  if (win_first >= win_last) return;
+  const int npos = COLS + K + 8;            // window elements (with alignment slack), <= 64 * MAXLD
+
+  // Loads of one window into registers (lane x covers positions lane + 64 i).
+  float2 pre[MAXLD];
+  auto load_window = [&](int64_t win) {
+    const int64_t bin0 = win * COLS - hg + 1;
+#pragma unroll
+    for (int i = 0; i < MAXLD; ++i) {
+      const int x = lane + 64 * i;
       const int64_t bin = bin0 + x;
-      float2 v = make_float2(0.f, 0.f);
-      if (bin >= 0 && bin < a.nbins) v = a.spec[bin];
-      uint16_t parts[4];
-      if constexpr (SPLIT) {
-        parts[0] = bf16_rne(v.x);
-        parts[1] = bf16_rne(v.y);
-        parts[2] = bf16_rne(v.x - bf16_to_f32(parts[0]));
-        parts[3] = bf16_rne(v.y - bf16_to_f32(parts[1]));
-      } else {
-        parts[0] = f16_bits(v.x);
-        parts[1] = f16_bits(v.y);
-      }
+      pre[i] = (x < npos && bin >= 0 && bin < a.nbins) ? a.spec[bin] : make_float2(0.f, 0.f);
+    }
+  };
+  // Split and store a loaded window into LDS buffer `buf`.
+  auto store_window = [&](int buf) {
+    uint16_t* l16 = reinterpret_cast<uint16_t*>(lds32 + buf * buf_words);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int xs = x - s;  // copy s holds element xs + s at index xs
-        if (xs >= 0 && xs < stride) {
+    for (int i = 0; i < MAXLD; ++i) {
+      const int x = lane + 64 * i;
+      if (x < npos) {
+        uint16_t parts[4];
+        if constexpr (SPLIT) {
+          parts[0] = bf16_rne(pre[i].x);
+          parts[1] = bf16_rne(pre[i].y);
+          parts[2] = bf16_rne(pre[i].x - bf16_to_f32(parts[0]));
+          parts[3] = bf16_rne(pre[i].y - bf16_to_f32(parts[1]));
+        } else {
+          parts[0] = f16_bits(pre[i].x);
+          parts[1] = f16_bits(pre[i].y);
+        }
 #pragma unroll
-          for (int pp = 0; pp < n_parts<SPLIT>(); ++pp) lds[(pp * 8 + s) * stride + xs] = parts[pp];
+        for (int pp = 0; pp < NPART; ++pp) {
+          // copy 0: element x at index x; copy 1: element x at index x - 1
+          l16[(pp * 2 + 0) * 2 * WW + x] = parts[pp];
+          if (x >= 1) l16[(pp * 2 + 1) * 2 * WW + x - 1] = parts[pp];
         }
       }
     }
-    __syncthreads();
+  };
 
-    f32x16 acc[RB][kColTiles];
+  // Tap fragments stay resident across windows when the group fits in KC
+  // k-steps (RESIDENT: the host guarantees KS <= KC).
+  uint4 afr[RB][KC][P];
+  auto load_frags = [&](int ks0) {
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int c = 0; c < kColTiles; ++c)
+      for (int q = 0; q < KC; ++q)
+#pragma unroll
+        for (int pp = 0; pp < P; ++pp)
+          afr[r][q][pp] = (ks0 + q < KS) ? *frag_ptr(rb0 + r, ks0 + q, pp) : make_uint4(0, 0, 0, 0);
+  };
+  if constexpr (RESIDENT) load_frags(0);
+
+  const int col = lane & 31;
+  const int shift = col & 1;
+  const int khalf = (lane >> 5) * 8;
+
+  load_window(win_first);
+  store_window(0);
+  __syncthreads();
+  for (int64_t win = win_first; win < win_last; ++win) {
+    const int buf = (int)((win - win_first) & 1);
+    if (win + 1 < win_last) load_window(win + 1);  // in flight during the MFMAs
+    const uint32_t* lb = lds32 + buf * buf_words;
+
+    f32x16 acc[RB][CT];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.f;
 
-    const int col = lane & 31;
-    const int shift = col & 7;
-    const int khalf = (lane >> 5) * 8;
-    for (int ks0 = 0; ks0 < KS; ks0 += kKsChunk) {
-      // tap fragments of this chunk
-      uint4 afr[RB][kKsChunk][P];
+    for (int ks0 = 0; ks0 < KS; ks0 += KC) {
+      if constexpr (!RESIDENT) load_frags(ks0);
 #pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int q = 0; q < kKsChunk; ++q)
-#pragma unroll
-          for (int pp = 0; pp < P; ++pp) {
-            const int ks = ks0 + q;
-            if (ks < KS) afr[r][q][pp] = *reinterpret_cast<const uint4*>(frag_ptr(rb_base_global + rb_first + r, ks, pp));
-            else afr[r][q][pp] = make_uint4(0, 0, 0, 0);
-          }
-#pragma unroll
-      for (int q = 0; q < kKsChunk; ++q) {
+      for (int q = 0; q < KC; ++q) {
         const int ks = ks0 + q;
         if (ks >= KS) break;
         const bool imag = ks >= ksr;
-        const int koff = (imag ? ks - ksr : ks) * 16 + khalf;  // tap offset of this lane's 8 values
+        const int koff = (imag ? ks - ksr : ks) * 16 + khalf;
+        const int p_re = imag ? 1 : 0;
 #pragma unroll
-        for (int c = 0; c < kColTiles; ++c) {
-          const int x = c * 32 + col + koff;  // window position of the first value
-          const int xa = x - shift;            // aligned index in copy 'shift'
-          const int p_hi = imag ? 1 : 0;
-          const uint4 bhi = *reinterpret_cast<const uint4*>(&lds[(p_hi * 8 + shift) * stride + xa]);
+        for (int c = 0; c < CT; ++c) {
+          const int x = c * 32 + col + koff;          // first element of this lane's 8
+          const int w0 = (x - shift) >> 1;             // word index in copy `shift`
+          const uint32_t* ph = lb + (p_re * 2 + shift) * WW + w0;
+          const uint4 bhi = make_uint4(ph[0], ph[1], ph[2], ph[3]);
           if constexpr (SPLIT) {
-            const uint4 blo = *reinterpret_cast<const uint4*>(&lds[((p_hi + 2) * 8 + shift) * stride + xa]);
+            const uint32_t* pl = lb + ((p_re + 2) * 2 + shift) * WW + w0;
+            const uint4 blo = make_uint4(pl[0], pl[1], pl[2], pl[3]);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
               acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, afr[r][q][0]),
@@ -169,28 +196,30 @@ __global__ void __launch_bounds__(64 * kWaves) gemm_correlate_kernel(GemmArgs a,
       }
     }
     // ---- epilogue: |Y|^2 for both phases, one float2 per (template, k0) ----
+    const int64_t col0 = win * COLS;
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m_local = (rb_first + r) * 8 + 2 * q + (lane >> 5);
+        const int m_local = (tblk * RB + r) * 8 + 2 * q + (lane >> 5);
         if (m_local >= n_members) continue;
         const int t = a.members[a.m_begin + m_local];
         if (t < a.t_begin || t >= a.t_end) continue;
-        float* row = a.plane + (int64_t)(t - a.t_begin) * a.ld;
+        float2* __restrict__ row = reinterpret_cast<float2*>(a.plane + (int64_t)(t - a.t_begin) * a.ld) + col0;
+        const int lim = (int)min((int64_t)COLS, a.nbins - col0);
 #pragma unroll
-        for (int c = 0; c < kColTiles; ++c) {
-          const int64_t k0 = col0 + c * 32 + col;
-          if (k0 < a.nbins) {
+        for (int c = 0; c < CT; ++c) {
+          const int j = c * 32 + col;
+          if (j < lim) {
             const f32x16& z = acc[r][c];
-            const float p0 = fmaf(z[4 * q], z[4 * q], z[4 * q + 1] * z[4 * q + 1]);
-            const float p1 = fmaf(z[4 * q + 2], z[4 * q + 2], z[4 * q + 3] * z[4 * q + 3]);
-            *reinterpret_cast<float2*>(row + 2 * k0) = make_float2(p0, p1);
+            row[j] = make_float2(fmaf(z[4 * q], z[4 * q], z[4 * q + 1] * z[4 * q + 1]),
+                                 fmaf(z[4 * q + 2], z[4 * q + 2], z[4 * q + 3] * z[4 * q + 3]));
           }
         }
       }
     }
-    __syncthreads();  // LDS is refilled for the next window
+    if (win + 1 < win_last) store_window(buf ^ 1);
+    __syncthreads();
   }
 }
 
@@ -245,7 +274,8 @@ __global__ void gemm_frag_kernel(const double2* __restrict__ taps, uint16_t* __r
 
 size_t gemm_bank_bytes(int32_t n_members, int32_t taps, int32_t path) {
   const size_t P = path == JERK_PATH_GEMM_FP16 ? 1 : 2;
-  const size_t n_rb = ((size_t)n_members + 7) / 8 + 2 * kWaves;  // padded: a workgroup may read past the end
+  // padded: the last workgroup of a member range may read up to kFragKsPad row blocks past the end
+  const size_t n_rb = ((size_t)n_members + 7) / 8 + kFragKsPad;
   return n_rb * (2 * (size_t)taps / 16) * P * 64 * 8 * sizeof(uint16_t);
 }
 
@@ -260,37 +290,48 @@ void gemm_bank_build(const Plan& p, const Group& g, const double2* taps, void* o
   JERK_HIP_CHECK(hipGetLastError());
 }
 
+namespace {
+
+template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT>
+void launch_cfg(const GemmArgs& a, hipStream_t stream) {
+  const int n_members = a.m_end - a.m_begin;
+  constexpr int COLS = window_cols<CT>();
+  const int64_t n_win = (a.nbins + COLS - 1) / COLS;
+  const int64_t n_tblk = (n_members + 8 * RB - 1) / (8 * RB);
+  // about 4 waves' worth of workgroups per CU slot; each walks consecutive windows
+  int64_t windows_per_wg = 1;
+  while (n_tblk * ((n_win + windows_per_wg - 1) / windows_per_wg) > 4096 && windows_per_wg < 256) windows_per_wg *= 2;
+  const int64_t n_colchunks = (n_win + windows_per_wg - 1) / windows_per_wg;
+  const int64_t blocks = n_tblk * n_colchunks;
+  require(blocks < (1ll << 31), JERK_EINVAL, "search too large for one launch");
+  require(COLS + a.taps + 8 <= 64 * MAXLD, JERK_EINTERNAL, "GEMM window larger than the per-lane load budget");
+  require(!RESIDENT || 2 * a.taps / 16 <= KC, JERK_EINTERNAL, "resident tap fragments exceed the register budget");
+  const size_t lds = (size_t)2 * (SPLIT ? 4 : 2) * 2 * win_words(COLS, a.taps) * sizeof(uint32_t);
+  hipLaunchKernelGGL((gemm_correlate_kernel<RB, CT, KC, MAXLD, SPLIT, RESIDENT>), dim3((unsigned)blocks), dim3(64), lds, stream, a,
+                     windows_per_wg, n_colchunks);
+}
+
+}  // namespace
+
 void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream) {
   const int n_members = a.m_end - a.m_begin;
   if (n_members <= 0 || a.nbins <= 0) return;
   require(a.m_begin % 8 == 0, JERK_EINTERNAL, "GEMM member range must start on a block of 8");
   require(a.taps % 16 == 0 && a.taps >= 16 && a.taps <= 512, JERK_EINTERNAL, "GEMM taps out of range");
   const bool split = a.path != JERK_PATH_GEMM_FP16;
-  const int stride = win_stride(a.taps);
-  const size_t lds_bytes = (size_t)n_parts<true>() * 8 * stride * sizeof(uint16_t);
-  const size_t lds_use = split ? lds_bytes : lds_bytes / 2;
-  const int64_t n_win = (a.nbins + kWin - 1) / kWin;
-  // RB = 2 row blocks per wave for narrow groups (fewer tap-fragment loads per MFMA), 1 otherwise.
-  const int RB = n_members > 8 * kWaves ? 2 : 1;
-  const int64_t templates_per_wg = (int64_t)8 * kWaves * RB;
-  const int64_t n_tblk = (n_members + templates_per_wg - 1) / templates_per_wg;
-  // Enough workgroups to fill the chip several times over; each walks consecutive windows.
-  int64_t windows_per_wg = 1;
-  while (n_tblk * ((n_win + windows_per_wg - 1) / windows_per_wg) > 8192 && windows_per_wg < 64) windows_per_wg *= 2;
-  const int64_t n_colchunks = (n_win + windows_per_wg - 1) / windows_per_wg;
-  const int64_t blocks = n_tblk * n_colchunks;
-  require(blocks < (1ll << 31), JERK_EINVAL, "search too large for one launch");
-  dim3 grid((unsigned)blocks), block(64 * kWaves);
+  // Row blocks per wave: 2 while the group has enough templates and the tap
+  // fragments of 64 taps fit in registers, 1 otherwise.
+  const bool two = n_members > 8 && a.taps <= 64;
+  // window = 64 outputs + taps + 8 slack elements, loaded 64 per lane-step
   if (split) {
-    if (RB == 2)
-      hipLaunchKernelGGL((gemm_correlate_kernel<2, true>), grid, block, lds_use, stream, a, windows_per_wg, n_colchunks);
-    else
-      hipLaunchKernelGGL((gemm_correlate_kernel<1, true>), grid, block, lds_use, stream, a, windows_per_wg, n_colchunks);
+    if (two) launch_cfg<2, 2, 8, 3, true, true>(a, stream);
+    else if (a.taps <= 128) launch_cfg<1, 2, 16, 4, true, true>(a, stream);
+    else if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false>(a, stream);
+    else launch_cfg<1, 2, 8, 10, true, false>(a, stream);
   } else {
-    if (RB == 2)
-      hipLaunchKernelGGL((gemm_correlate_kernel<2, false>), grid, block, lds_use, stream, a, windows_per_wg, n_colchunks);
-    else
-      hipLaunchKernelGGL((gemm_correlate_kernel<1, false>), grid, block, lds_use, stream, a, windows_per_wg, n_colchunks);
+    if (two) launch_cfg<2, 2, 8, 3, false, true>(a, stream);
+    else if (a.taps <= 256) launch_cfg<1, 2, 32, 6, false, true>(a, stream);
+    else launch_cfg<1, 2, 16, 10, false, false>(a, stream);
   }
   JERK_HIP_CHECK(hipGetLastError());
 }

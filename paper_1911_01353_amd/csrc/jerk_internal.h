@@ -49,6 +49,10 @@ struct Group {
   size_t gemm_bytes = 0;
 };
 
+// Host state of batched launches of one plan (staging buffer, capture stream, graph).
+struct BatchCtx;
+void batch_ctx_free(BatchCtx* c);
+
 struct Plan {
   jerk_plan_desc desc{};
   int32_t n_z = 0, n_w = 0, J = 0, T = 0;
@@ -64,6 +68,7 @@ struct Plan {
   int32_t max_taps = 0;
   // Gauss-Legendre rule on [-1, 1] used by the template generator.
   double gl_x[16], gl_w[16];
+  BatchCtx* batch = nullptr;
 };
 
 // plan.cpp
@@ -75,20 +80,38 @@ bool seg_len_supported(int32_t s);
 // templates.hip
 void templates_build(const Plan& p, void* d_bank, hipStream_t stream);
 
-// fft_correlate.hip: one width group, member range [m_begin, m_end) of the group.
-struct FftArgs {
+// fft_correlate.hip. One FFT-path job: one spectrum, one width group, the
+// group's member range [m_begin, m_end), every segment.
+struct FftJob {
   const float2* spec;
   int64_t nbins;
   const float2* bank_fft;     // group's spectra, member 0 phase 0
   const int32_t* members;     // group's member list (device)
   int32_t m_begin, m_end;     // members to process
-  int32_t t_begin;            // plane row of template t is (t - t_begin)
-  float* plane;
+  int32_t t_begin;            // output row of template t is t - t_begin
+  int32_t taps, tpb;
+  float* plane;               // plane rows (row stride ld floats), or null
   int64_t ld;
-  int32_t taps, seg_len, tpb;
+  uint64_t* row_max;          // peak keys [row][segment] (row stride rmax_ld), or null
+  int64_t rmax_ld;
+  int64_t n_seg;              // set by fft_job_tiles
+  int64_t tile_begin;         // first tile of the job in a persistent launch
 };
+// Header of a persistent launch's work list (device memory).
+struct BatchHeader {
+  int64_t total_tiles;
+  unsigned long long counter;
+  int32_t n_jobs;
+  int32_t pad;
+};
+// Sets j.n_seg and returns the job's tile count (segments x template blocks).
+int64_t fft_job_tiles(FftJob& j, int32_t seg_len);
 // twiddles: exp(-2 pi i k / seg_len), k < seg_len (complex64, device).
-void fft_correlate_launch(const FftArgs& a, const float2* twiddles, hipStream_t stream);
+void fft_correlate_launch(FftJob j, int32_t seg_len, const float2* twiddles, hipStream_t stream);
+void fft_persistent_launch(const FftJob* d_jobs, BatchHeader* d_hdr, int32_t seg_len, const float2* twiddles,
+                           int32_t grid, hipStream_t stream);
+// Workgroups of the persistent kernel that fit on the current device at once.
+int32_t fft_persistent_grid(int32_t seg_len);
 
 // gemm_correlate.hip
 struct GemmArgs {
@@ -105,6 +128,16 @@ struct GemmArgs {
 };
 void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream);
 size_t gemm_bank_bytes(int32_t n_members, int32_t taps, int32_t path);
+
+// batch.cpp
+size_t batch_workspace_bytes(const Plan& p, int32_t count);
+int64_t batch_keys_per_row(const Plan& p, int64_t nbins);
+void batch_search(Plan& p, const void* d_bank, const jerk_batch_item* items, int32_t count, int32_t t_begin,
+                  int32_t t_end, void* d_ws, size_t ws_bytes, uint32_t flags, hipStream_t stream);
+
+// reduce.hip
+void peaks_reduce(const uint64_t* keys, int32_t rows, int64_t per_row, int64_t ld, jerk_peak* out,
+                  hipStream_t stream);
 
 // Error-reporting state of the C ABI.
 void set_last_error(const std::string& msg);

@@ -115,3 +115,25 @@ def test_search_argument_errors_are_synchronous():
     assert lib.jerk_templates_build(p.handle, fake, 16, null) == J.JERK_ENOMEM
     # NULL plan everywhere
     assert lib.jerk_plan_info(None, None) == J.JERK_EINVAL
+
+
+def test_batch_argument_errors_without_gpu():
+    lib = J.load()
+    fake = C.c_void_p(0x100000)
+    null = C.c_void_p(0)
+    item = (J._lib.BatchItem * 1)()
+    item[0].spec = 0x100000
+    item[0].nbins = 4096
+    item[0].plane = 0x200000
+    item[0].ld = 8192
+    auto = J.Plan(4096, 20, 60, path="auto")   # MFMA groups: not batchable
+    assert lib.jerk_batch_search(auto.handle, fake, item, 1, 0, 147, fake, 1 << 20, 0, null) == J.JERK_EINVAL
+    fft = J.Plan(4096, 20, 60, path="fft", seg_len=1024)
+    need = lib.jerk_batch_workspace_bytes(fft.handle, 1)
+    assert need > 0
+    assert lib.jerk_batch_search(fft.handle, fake, item, 1, 0, 147, fake, need - 1, 0, null) == J.JERK_ENOMEM
+    assert lib.jerk_batch_search(fft.handle, fake, item, 1, 0, 147, fake, need, 7, null) == J.JERK_EINVAL
+    item[0].ld = 100
+    assert lib.jerk_batch_search(fft.handle, fake, item, 1, 0, 147, fake, need, 0, null) == J.JERK_EINVAL
+    # one key per FFT segment of the narrowest-output (widest) group
+    assert fft.keys_per_row(4096) == -(-4096 // (1024 - 64 + 1))

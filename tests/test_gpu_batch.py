@@ -1,0 +1,117 @@
+"""GPU tests of the batched persistent launch, its hipGraph replay and the peak reduction."""
+
+import numpy as np
+import pytest
+
+import paper_1911_01353_amd as J
+from oracle import Grid, error_summary, oracle_plane
+
+from gpu_helpers import build_bank, device, gpu_plane
+
+pytestmark = pytest.mark.gpu
+
+LENGTHS = [1 << 14, 3000, 1 << 15, 1, 777, 20000]
+
+
+def _spectra(lengths, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in lengths:
+        x = ((rng.standard_normal(n) + 1j * rng.standard_normal(n)) / np.sqrt(2)).astype(np.complex64)
+        out.append(x)
+    return out
+
+
+def _row_peaks(plane):
+    """Host peak of each row: largest FP32 power, lowest index on ties."""
+    idx = np.argmax(plane, axis=1)
+    return plane[np.arange(plane.shape[0]), idx], idx
+
+
+def _run_batch(plan, bank, specs_np, graph, t_begin, t_end, with_keys=True, ws=None):
+    import torch
+    dev = device()
+    rows = t_end - t_begin
+    specs = [torch.from_numpy(s).to(dev) for s in specs_np]
+    planes = [torch.full((rows, 2 * s.shape[0] + 4), float("nan"), dtype=torch.float32, device=dev) for s in specs_np]
+    keys = [torch.zeros((rows, plan.keys_per_row(s.shape[0]) + 3), dtype=torch.int64, device=dev) if with_keys
+            else None for s in specs_np]
+    if ws is None:
+        ws = torch.empty(plan.batch_workspace_bytes(len(specs)), dtype=torch.uint8, device=dev)
+    plan.batch_search(bank, list(zip(specs, planes, keys)), ws, t_begin, t_end, graph=graph)
+    torch.cuda.synchronize()
+    out = []
+    for s, pl, k in zip(specs_np, planes, keys):
+        pk = None
+        if k is not None:
+            red = torch.empty((rows, 2), dtype=torch.int32, device=dev)
+            J.peaks_reduce(k, plan.keys_per_row(s.shape[0]), red)
+            torch.cuda.synchronize()
+            r = red.cpu().numpy()
+            pk = (r[:, 0].view(np.float32).copy(), r[:, 1].view(np.uint32).astype(np.int64))
+        out.append((pl.cpu().numpy()[:, : 2 * s.shape[0]], pk))
+    return out
+
+
+@pytest.fixture(scope="module")
+def plan_bank():
+    device()
+    plan = J.Plan(1 << 15, 20.0, 60.0, 2.0, 20.0, path="fft", seg_len=1024)
+    return plan, build_bank(plan)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_single_searches(plan_bank, graph):
+    plan, bank = plan_bank
+    specs = _spectra(LENGTHS, 11)
+    T = plan.info()["n_templates"]
+    res = _run_batch(plan, bank, specs, graph, 0, T)
+    for s, (pl, (pw, pp)) in zip(specs, res):
+        ref = gpu_plane(plan, bank, s)
+        assert not np.isnan(pl).any()
+        assert np.array_equal(pl.view(np.uint32), ref.view(np.uint32)), s.shape
+        hp, hi = _row_peaks(ref)
+        assert np.array_equal(pw, hp) and np.array_equal(pp, hi)
+
+
+def test_batch_template_slab_and_oracle(plan_bank):
+    plan, bank = plan_bank
+    specs = _spectra([5000, 1234], 12)
+    res = _run_batch(plan, bank, specs, False, 40, 90)
+    grid = Grid(20.0, 60.0, 2.0, 20.0)
+    for s, (pl, _) in zip(specs, res):
+        ora = oracle_plane(s, grid, templates=range(40, 90))
+        assert error_summary(pl, ora)["max"] <= 1e-4
+
+
+def test_graph_replays_match_eager(plan_bank):
+    """Replays of one captured graph with new job tables, with eager work in between."""
+    import torch
+    plan, bank = plan_bank
+    T = plan.info()["n_templates"]
+    dev = device()
+    rng_lengths = [[4096, 999, 30000], [17, 8192], [30000, 4096, 999, 5, 12345]]
+    ws = torch.empty(plan.batch_workspace_bytes(8), dtype=torch.uint8, device=dev)  # one graph for all replays
+    for k, lengths in enumerate(rng_lengths):
+        specs = _spectra(lengths, 100 + k)
+        # unrelated eager work on the same stream between replays
+        junk = torch.randn(1 << 20, device=dev)
+        _ = (junk * 2).sum().item()
+        got = _run_batch(plan, bank, specs, True, 0, T, ws=ws)
+        want = _run_batch(plan, bank, specs, False, 0, T)
+        for (a, pa), (b, pb) in zip(got, want):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+            assert np.array_equal(pa[0], pb[0]) and np.array_equal(pa[1], pb[1])
+
+
+def test_batch_rejects_mixed_paths():
+    device()
+    plan = J.Plan(4096, 20.0, 60.0, 2.0, 20.0, path="auto")
+    bank = build_bank(plan)
+    import torch
+    ws = torch.empty(plan.batch_workspace_bytes(1), dtype=torch.uint8, device="cuda")
+    spec = torch.zeros(4096, dtype=torch.complex64, device="cuda")
+    plane = torch.zeros((147, 8192), dtype=torch.float32, device="cuda")
+    with pytest.raises(J.JerkError) as ei:
+        plan.batch_search(bank, [(spec, plane, None)], ws)
+    assert ei.value.status == J.JERK_EINVAL
