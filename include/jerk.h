@@ -56,6 +56,7 @@ extern "C" {
 #define JERK_EHIP (-5)         /* a HIP runtime call failed                      */
 #define JERK_EUNSUPPORTED (-6) /* valid but not supported by this build          */
 #define JERK_EINTERNAL (-7)    /* library bug                                    */
+#define JERK_ECANCELED (-8)    /* request dropped (server destroyed before it ran) */
 
 /* ---- correlation paths ------------------------------------------------- */
 #define JERK_PATH_FFT_FP32 0       /* fused overlap-save FFT, FP32                  */
@@ -127,6 +128,22 @@ int32_t jerk_plan_members(const jerk_plan* plan, int32_t* out, int32_t count);
 int32_t jerk_plan_set_group(jerk_plan* plan, int32_t g, int32_t seg_len,
                             int32_t templates_per_block, int32_t path);
 
+/* ---- autotuner -------------------------------------------------------------- */
+#define JERK_TUNE_UNIFORM 1u /* one FFT segment length for all groups (for jerk_batch_search) */
+
+/* Device scratch bytes jerk_plan_autotune needs for a probe spectrum of nbins bins. */
+size_t jerk_autotune_scratch_bytes(const jerk_plan* plan, int64_t nbins);
+/* For every width group, times the candidate kernels on up to 32 of the group's templates over
+ * the first min(nbins, 2^20) bins of d_spec: the FFT path with segment lengths 512..4096
+ * (at least twice the group width) and 8 or 16 templates per workgroup, and for
+ * JERK_PATH_AUTO plans also the split-BF16 MFMA path. Keeps the fastest per output point
+ * (JERK_TUNE_UNIFORM: FFT only, one segment length minimising the estimated total). Call
+ * before jerk_templates_build; bank_bytes may change. Synchronous (waits on stream). Choices
+ * are cached per process by (device, group width, probe size, candidate set). Plans with a
+ * fixed MFMA path are left unchanged. */
+int32_t jerk_plan_autotune(jerk_plan* plan, const void* d_spec, int64_t nbins, void* d_scratch,
+                           size_t scratch_bytes, uint32_t flags, hipStream_t stream);
+
 /* ---- template bank (FP64 generation on the GPU) -------------------------- */
 /* Generates every template's taps in FP64 by composite Gauss-Legendre quadrature of R
  * (16 nodes per panel, at most one phase cycle per panel) and derives the bank of each
@@ -191,6 +208,70 @@ typedef struct jerk_peak {
  * Rows whose keys were all left 0 report power 0 and p = 0xFFFFFFFF. Asynchronous on stream. */
 int32_t jerk_peaks_reduce(const uint64_t* d_keys, int32_t rows, int64_t keys_per_row, int64_t keys_ld,
                           jerk_peak* d_out, hipStream_t stream);
+
+/* ---- serving: continuous batching of search requests ----------------------- */
+typedef struct jerk_server jerk_server;
+
+#define JERK_SERVE_DRYRUN 1u /* host-only scheduler test mode: no device calls, tiles finish at once */
+
+typedef struct jerk_serve_desc {
+  int32_t max_active;       /* requests admitted to the device at once (>= 1)                      */
+  int32_t queue_capacity;   /* submitted, not yet admitted (>= 1); submit returns EAGAIN when full */
+  int64_t tiles_per_launch; /* scheduling quantum: FFT tiles per launch over all requests (0 = auto) */
+  int32_t seg_len;          /* FFT segment length of serving plans (0 = per-group default)          */
+  int32_t slots;            /* launches in flight at once, each on its own stream (1..8, 0 = 3)     */
+  uint32_t flags;           /* JERK_SERVE_* */
+  int32_t reserved;
+} jerk_serve_desc;
+
+typedef struct jerk_request {
+  const void* spec;        /* device complex64 spectrum [nbins]; caller-owned, valid until done  */
+  int64_t nbins;
+  double zmax, wmax, dz, dw; /* lattice (margin 16 bins, two outputs per bin)                   */
+  int32_t path;            /* JERK_PATH_FFT_FP32 or JERK_PATH_GEMM_SPLIT_BF16                     */
+  int32_t peaks_capacity;  /* entries of `peaks`                                                  */
+  float* plane;            /* optional device buffer for the plane, rows t x 2 nbins at stride ld */
+  int64_t ld;
+  jerk_peak* peaks;        /* optional host array: per-template peaks, filled on completion       */
+} jerk_request;
+
+typedef struct jerk_result {
+  int32_t status;          /* JERK_OK or the error that ended the request                        */
+  int32_t n_templates;
+  float best_power;        /* global peak: largest power, ties to the lowest (t, p)              */
+  int32_t best_t;
+  uint32_t best_p;         /* r index of the peak (r = p / 2)                                    */
+  int32_t reserved;
+  uint64_t points;         /* plane points searched (2 nbins x n_templates)                      */
+  double t_submit, t_admit, t_first_launch, t_done; /* seconds on the server's steady clock    */
+} jerk_result;
+
+typedef struct jerk_serve_stats {
+  uint64_t submitted, completed, failed, launches, bank_builds, bank_evictions;
+  int32_t queued, active;
+  size_t arena_used, arena_bytes;
+} jerk_serve_stats;
+
+/* Creates a server whose scheduler thread runs requests on the current device. d_arena
+ * (caller device memory, 256-byte aligned) holds the template-bank cache, per-request
+ * peak buffers and launch tables; requests are admitted while their footprint fits. */
+int32_t jerk_serve_create(const jerk_serve_desc* desc, void* d_arena, size_t arena_bytes, jerk_server** out);
+/* Queues a request without blocking. EAGAIN: queue full; ENOMEM: can never fit the arena;
+ * EINVAL: bad request. Requests that arrive while others run are admitted as slots and
+ * arena memory free up; their tiles are interleaved with the running requests' tiles in the
+ * same launches (round-robin), and each result is independent of the mix. */
+int32_t jerk_serve_submit(jerk_server* srv, const jerk_request* req, uint64_t* ticket);
+/* EPENDING until the request is done, then JERK_OK with *out filled (out->status says how it ended). */
+int32_t jerk_serve_poll(jerk_server* srv, uint64_t ticket, jerk_result* out);
+/* As poll, blocking up to timeout_s seconds (< 0: no limit). */
+int32_t jerk_serve_wait(jerk_server* srv, uint64_t ticket, jerk_result* out, double timeout_s);
+int32_t jerk_serve_stats_get(jerk_server* srv, jerk_serve_stats* out);
+/* Test hooks: op 1 fails the n-th launch from now (counting from 1), op 2 the n-th bank build;
+ * the requests involved end with JERK_EHIP and the others continue; n = 0 disarms. op 3 holds
+ * admission while n != 0 (queued requests stay queued) and releases it with n = 0. */
+int32_t jerk_serve_inject_failure(jerk_server* srv, int32_t op, int64_t n);
+/* Stops the scheduler after the work on the device finishes; queued requests end JERK_ECANCELED. */
+int32_t jerk_serve_destroy(jerk_server* srv);
 
 #ifdef __cplusplus
 }

@@ -13,11 +13,11 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (JERK_EAGAIN, JERK_EINVAL, JERK_ENOMEM, JERK_EPENDING, JERK_OK, PATH_AUTO, PATH_FFT_FP32,
-                   PATH_GEMM_FP16, PATH_GEMM_SPLIT_BF16, PATH_NAMES, JerkError)
+from ._lib import (JERK_EAGAIN, JERK_ECANCELED, JERK_EHIP, JERK_EINVAL, JERK_ENOMEM, JERK_EPENDING, JERK_OK,
+                   PATH_AUTO, PATH_FFT_FP32, PATH_GEMM_FP16, PATH_GEMM_SPLIT_BF16, PATH_NAMES, JerkError)
 
 __all__ = [
-    "Plan", "peaks_reduce", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
+    "Plan", "Server", "peaks_reduce", "JERK_EHIP", "JERK_ECANCELED", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
     "PATH_AUTO", "PATH_NAMES", "JERK_OK", "JERK_EINVAL", "JERK_ENOMEM", "JERK_EAGAIN", "JERK_EPENDING",
 ]
 
@@ -147,6 +147,16 @@ class Plan:
         _lib.check(_lib.load().jerk_search_group(self.handle, _dev_ptr(bank), _dev_ptr(spec), n, _dev_ptr(plane),
                                                  plane.stride(0), t_begin, t_end, g, _stream_ptr(stream)))
 
+    def autotune(self, spec, uniform: bool = False, stream=None) -> None:
+        """Run ``jerk_plan_autotune`` on a device spectrum (synchronous); scratch from torch."""
+        import torch
+        n = spec.shape[0]
+        nbytes = int(_lib.load().jerk_autotune_scratch_bytes(self.handle, n))
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=spec.device)
+        _lib.check(_lib.load().jerk_plan_autotune(self.handle, _dev_ptr(spec), n, _dev_ptr(scratch), nbytes,
+                                                  _lib.TUNE_UNIFORM if uniform else 0, _stream_ptr(stream)))
+        del scratch
+
     # -- batched search -----------------------------------------------------------
     def batch_workspace_bytes(self, count: int) -> int:
         return int(_lib.load().jerk_batch_workspace_bytes(self.handle, count))
@@ -200,3 +210,92 @@ def peaks_reduce(keys, keys_per_row: int, out, stream=None) -> None:
     rows = keys.shape[0]
     _lib.check(_lib.load().jerk_peaks_reduce(_dev_ptr(keys), rows, keys_per_row, keys.stride(0), _dev_ptr(out),
                                              _stream_ptr(stream)))
+
+
+class Server:
+    """``jerk_serve_*``: continuous-batching request server on the current device.
+
+    ``arena``: a 256-byte-aligned device buffer (e.g. a torch uint8 tensor) the server
+    sub-allocates, or an integer address with ``dry_run=True`` (host-only scheduler test).
+    """
+
+    def __init__(self, arena, arena_bytes: int | None = None, max_active: int = 4, queue_capacity: int = 64,
+                 tiles_per_launch: int = 0, seg_len: int = 0, slots: int = 0, dry_run: bool = False):
+        lib = _lib.load()
+        if isinstance(arena, int):
+            ptr, nbytes = C.c_void_p(arena), arena_bytes
+        else:
+            ptr, nbytes = _dev_ptr(arena), arena.numel() * arena.element_size()
+        self._arena = arena  # keep the buffer alive
+        d = _lib.ServeDesc(max_active=max_active, queue_capacity=queue_capacity, tiles_per_launch=tiles_per_launch,
+                           seg_len=seg_len, slots=slots, flags=_lib.SERVE_DRYRUN if dry_run else 0)
+        h = C.c_void_p()
+        _lib.check(lib.jerk_serve_create(C.byref(d), ptr, nbytes, C.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, spec, zmax: float, wmax: float, dz: float = 2.0, dw: float = 20.0, path="fft", plane=None,
+               n_templates: int | None = None, nbins: int | None = None) -> int:
+        """Queue a request; returns its ticket. ``spec``: device complex64 tensor (or an address with ``nbins``)."""
+        if isinstance(path, str):
+            path = PATH_NAMES[path]
+        if isinstance(spec, int):
+            sp, n = spec, nbins
+        else:
+            sp, n = _dev_ptr(spec).value, spec.shape[0]
+        peaks = None
+        if n_templates:
+            peaks = (_lib.Peak * n_templates)()
+        r = _lib.Request(spec=sp, nbins=n, zmax=zmax, wmax=wmax, dz=dz, dw=dw, path=path,
+                         peaks_capacity=n_templates or 0,
+                         plane=_dev_ptr(plane).value if plane is not None else None,
+                         ld=plane.stride(0) if plane is not None else 0,
+                         peaks=C.cast(peaks, C.c_void_p) if peaks is not None else None)
+        t = C.c_uint64()
+        _lib.check(_lib.load().jerk_serve_submit(self._h, C.byref(r), C.byref(t)))
+        self._keep[t.value] = (spec, plane, peaks)
+        return t.value
+
+    def _result(self, res, ticket):
+        out = {f: getattr(res, f) for f, _ in res._fields_}
+        spec, plane, peaks = self._keep.get(ticket, (None, None, None))
+        if peaks is not None:
+            arr = np.frombuffer(peaks, dtype=np.dtype([("power", np.float32), ("p", np.uint32)])).copy()
+            out["peaks_power"] = arr["power"]
+            out["peaks_p"] = arr["p"]
+        return out
+
+    def poll(self, ticket: int):
+        res = _lib.Result()
+        st = _lib.load().jerk_serve_poll(self._h, ticket, C.byref(res))
+        if st == JERK_EPENDING:
+            return None
+        _lib.check(st)
+        return self._result(res, ticket)
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        res = _lib.Result()
+        st = _lib.load().jerk_serve_wait(self._h, ticket, C.byref(res), timeout_s)
+        if st == JERK_EPENDING:
+            return None
+        _lib.check(st)
+        return self._result(res, ticket)
+
+    def stats(self) -> dict:
+        out = _lib.ServeStats()
+        _lib.check(_lib.load().jerk_serve_stats_get(self._h, C.byref(out)))
+        return {f: getattr(out, f) for f, _ in out._fields_}
+
+    def inject_failure(self, op: int, n: int) -> None:
+        _lib.check(_lib.load().jerk_serve_inject_failure(self._h, op, n))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _lib.load().jerk_serve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

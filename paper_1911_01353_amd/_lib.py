@@ -21,6 +21,7 @@ JERK_EPENDING = -4
 JERK_EHIP = -5
 JERK_EUNSUPPORTED = -6
 JERK_EINTERNAL = -7
+JERK_ECANCELED = -8
 
 PATH_FFT_FP32 = 0
 PATH_GEMM_SPLIT_BF16 = 1
@@ -70,6 +71,39 @@ class Peak(C.Structure):
 
 
 BATCH_GRAPH = 1
+SERVE_DRYRUN = 1
+
+
+class ServeDesc(C.Structure):
+    _fields_ = [
+        ("max_active", C.c_int32), ("queue_capacity", C.c_int32), ("tiles_per_launch", C.c_int64),
+        ("seg_len", C.c_int32), ("slots", C.c_int32), ("flags", C.c_uint32), ("reserved", C.c_int32),
+    ]
+
+
+class Request(C.Structure):
+    _fields_ = [
+        ("spec", C.c_void_p), ("nbins", C.c_int64),
+        ("zmax", C.c_double), ("wmax", C.c_double), ("dz", C.c_double), ("dw", C.c_double),
+        ("path", C.c_int32), ("peaks_capacity", C.c_int32),
+        ("plane", C.c_void_p), ("ld", C.c_int64), ("peaks", C.c_void_p),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("n_templates", C.c_int32), ("best_power", C.c_float), ("best_t", C.c_int32),
+        ("best_p", C.c_uint32), ("reserved", C.c_int32), ("points", C.c_uint64),
+        ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_first_launch", C.c_double), ("t_done", C.c_double),
+    ]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [
+        ("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64), ("launches", C.c_uint64),
+        ("bank_builds", C.c_uint64), ("bank_evictions", C.c_uint64), ("queued", C.c_int32), ("active", C.c_int32),
+        ("arena_used", C.c_size_t), ("arena_bytes", C.c_size_t),
+    ]
 
 # name -> (restype, argtypes)
 SIGNATURES = {
@@ -94,7 +128,19 @@ SIGNATURES = {
     "jerk_batch_search": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(BatchItem), C.c_int32, C.c_int32, C.c_int32,
                                       C.c_void_p, C.c_size_t, C.c_uint32, C.c_void_p]),
     "jerk_peaks_reduce": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "jerk_serve_create": (C.c_int32, [C.POINTER(ServeDesc), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
+    "jerk_serve_submit": (C.c_int32, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "jerk_serve_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(Result)]),
+    "jerk_serve_wait": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(Result), C.c_double]),
+    "jerk_serve_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(ServeStats)]),
+    "jerk_serve_inject_failure": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64]),
+    "jerk_serve_destroy": (C.c_int32, [C.c_void_p]),
+    "jerk_autotune_scratch_bytes": (C.c_size_t, [C.c_void_p, C.c_int64]),
+    "jerk_plan_autotune": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_size_t, C.c_uint32,
+                                       C.c_void_p]),
 }
+
+TUNE_UNIFORM = 1
 
 _lib = None
 

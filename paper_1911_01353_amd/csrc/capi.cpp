@@ -105,6 +105,7 @@ const char* jerk_status_str(int32_t s) {
     case JERK_EHIP: return "JERK_EHIP";
     case JERK_EUNSUPPORTED: return "JERK_EUNSUPPORTED";
     case JERK_EINTERNAL: return "JERK_EINTERNAL";
+    case JERK_ECANCELED: return "JERK_ECANCELED";
     default: return "JERK_UNKNOWN";
   }
 }
@@ -225,20 +226,7 @@ int32_t jerk_templates_build(jerk_plan* plan, void* d_bank, size_t bank_bytes, h
     jerk::Plan& p = plan->p;
     require(bank_bytes >= p.bank_bytes, JERK_ENOMEM, "bank buffer smaller than bank_bytes");
     require(reinterpret_cast<uintptr_t>(d_bank) % 256 == 0, JERK_EINVAL, "bank must be 256-byte aligned");
-    if (!p.pinned_members) {
-      void* h = nullptr;
-      JERK_HIP_CHECK(hipHostMalloc(&h, sizeof(int32_t) * (size_t)p.T, hipHostMallocDefault));
-      p.pinned_members = static_cast<int32_t*>(h);
-      int32_t k = 0;
-      for (const auto& g : p.groups)
-        for (int32_t t : g.members) p.pinned_members[k++] = t;
-    }
-    char* bank = static_cast<char*>(d_bank);
-    JERK_HIP_CHECK(hipMemcpyAsync(bank + p.off_members, p.pinned_members, sizeof(int32_t) * (size_t)p.T,
-                                  hipMemcpyHostToDevice, stream));
-    for (int i = 0; i < 4; ++i)
-      jerk::gen_twiddles(reinterpret_cast<float2*>(bank + p.off_tw[i]), 512 << i, stream);
-    jerk::templates_build(p, d_bank, stream);
+    jerk::bank_build(p, d_bank, stream);
   });
 }
 
@@ -308,6 +296,72 @@ int32_t jerk_peaks_reduce(const uint64_t* d_keys, int32_t rows, int64_t keys_per
     if (rows == 0) return;
     require(d_keys && d_out, JERK_EINVAL, "keys and output must not be NULL");
     jerk::peaks_reduce(d_keys, rows, keys_per_row, keys_ld, d_out, stream);
+  });
+}
+
+size_t jerk_autotune_scratch_bytes(const jerk_plan* plan, int64_t nbins) {
+  if (!plan || nbins < 1) return 0;
+  return jerk::autotune_scratch_bytes(plan->p, nbins);
+}
+
+int32_t jerk_plan_autotune(jerk_plan* plan, const void* d_spec, int64_t nbins, void* d_scratch, size_t scratch_bytes,
+                           uint32_t flags, hipStream_t stream) {
+  return guarded([&] {
+    require(plan != nullptr, JERK_EINVAL, "plan must not be NULL");
+    jerk::autotune(plan->p, d_spec, nbins, d_scratch, scratch_bytes, flags, stream);
+  });
+}
+
+int32_t jerk_serve_create(const jerk_serve_desc* desc, void* d_arena, size_t arena_bytes, jerk_server** out) {
+  return guarded([&] {
+    require(desc != nullptr && out != nullptr, JERK_EINVAL, "desc and out must not be NULL");
+    *out = nullptr;
+    jerk::serve_create(*desc, d_arena, arena_bytes, out);
+  });
+}
+
+int32_t jerk_serve_submit(jerk_server* srv, const jerk_request* req, uint64_t* ticket) {
+  return guarded([&] {
+    require(srv && req && ticket, JERK_EINVAL, "server, request and ticket must not be NULL");
+    jerk::serve_submit(*srv, *req, ticket);
+  });
+}
+
+int32_t jerk_serve_poll(jerk_server* srv, uint64_t ticket, jerk_result* out) {
+  int32_t rc = JERK_OK;
+  const int32_t st = guarded([&] {
+    require(srv && out, JERK_EINVAL, "server and out must not be NULL");
+    rc = jerk::serve_poll(*srv, ticket, out, 0.0);
+  });
+  return st != JERK_OK ? st : rc;
+}
+
+int32_t jerk_serve_wait(jerk_server* srv, uint64_t ticket, jerk_result* out, double timeout_s) {
+  int32_t rc = JERK_OK;
+  const int32_t st = guarded([&] {
+    require(srv && out, JERK_EINVAL, "server and out must not be NULL");
+    rc = jerk::serve_poll(*srv, ticket, out, timeout_s);
+  });
+  return st != JERK_OK ? st : rc;
+}
+
+int32_t jerk_serve_stats_get(jerk_server* srv, jerk_serve_stats* out) {
+  return guarded([&] {
+    require(srv && out, JERK_EINVAL, "server and out must not be NULL");
+    jerk::serve_stats(*srv, out);
+  });
+}
+
+int32_t jerk_serve_inject_failure(jerk_server* srv, int32_t op, int64_t n) {
+  return guarded([&] {
+    require(srv != nullptr, JERK_EINVAL, "server must not be NULL");
+    jerk::serve_inject(*srv, op, n);
+  });
+}
+
+int32_t jerk_serve_destroy(jerk_server* srv) {
+  return guarded([&] {
+    if (srv) jerk::serve_destroy(srv);
   });
 }
 

@@ -259,7 +259,10 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int tb, f
         }
         if (j.row_max) {
           best = block_max_key<TPB>(best, red);
-          if (tid == 0) j.row_max[row * j.rmax_ld + seg] = best;
+          if (tid == 0) {
+            if (j.rmax_ld == 0) atomicMax(reinterpret_cast<unsigned long long*>(j.row_max + row), (unsigned long long)best);
+            else j.row_max[row * j.rmax_ld + seg] = best;
+          }
         }
       }
     }

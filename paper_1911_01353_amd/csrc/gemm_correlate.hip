@@ -59,7 +59,7 @@ __host__ __device__ constexpr int window_cols() { return 32 * CT; }
 // group and a run of consecutive windows of 32*CT outputs. Tap fragments for up
 // to KC k-steps stay in registers; the spectrum window is double-buffered in
 // LDS and the next window's loads are issued before the current window's MFMAs.
-template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT>
+template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT, bool KEYS>
 __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64_t windows_per_wg, int64_t n_colchunks) {
   extern __shared__ uint32_t lds32[];
   constexpr int P = SPLIT ? 2 : 1;        // parts of each operand (hi, lo)
@@ -143,6 +143,13 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
   const int shift = col & 1;
   const int khalf = (lane >> 5) * 8;
 
+  // peak keys of this lane's rows (template 2q + lane/32 of each row block), over all its windows
+  uint64_t best[KEYS ? RB : 1][4];
+#pragma unroll
+  for (int r = 0; r < (KEYS ? RB : 1); ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) best[r][q] = 0;
+
   load_window(win_first);
   store_window(0);
   __syncthreads();
@@ -205,21 +212,50 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
         if (m_local >= n_members) continue;
         const int t = a.members[a.m_begin + m_local];
         if (t < a.t_begin || t >= a.t_end) continue;
-        float2* __restrict__ row = reinterpret_cast<float2*>(a.plane + (int64_t)(t - a.t_begin) * a.ld) + col0;
+        float2* __restrict__ row =
+            a.plane ? reinterpret_cast<float2*>(a.plane + (int64_t)(t - a.t_begin) * a.ld) + col0 : nullptr;
         const int lim = (int)min((int64_t)COLS, a.nbins - col0);
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
           const int j = c * 32 + col;
           if (j < lim) {
             const f32x16& z = acc[r][c];
-            row[j] = make_float2(fmaf(z[4 * q], z[4 * q], z[4 * q + 1] * z[4 * q + 1]),
-                                 fmaf(z[4 * q + 2], z[4 * q + 2], z[4 * q + 3] * z[4 * q + 3]));
+            const float p0 = fmaf(z[4 * q], z[4 * q], z[4 * q + 1] * z[4 * q + 1]);
+            const float p1 = fmaf(z[4 * q + 2], z[4 * q + 2], z[4 * q + 3] * z[4 * q + 3]);
+            if (row) row[j] = make_float2(p0, p1);
+            if constexpr (KEYS) {
+              const int64_t p = 2 * (col0 + j);
+              const uint64_t k0 = ((uint64_t)__float_as_uint(p0) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)p);
+              const uint64_t k1 = ((uint64_t)__float_as_uint(p1) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)(p + 1));
+              const uint64_t kk = k1 > k0 ? k1 : k0;
+              best[r][q] = kk > best[r][q] ? kk : best[r][q];
+            }
           }
         }
       }
     }
     if (win + 1 < win_last) store_window(buf ^ 1);
     __syncthreads();
+  }
+  if constexpr (KEYS) {
+    // combine the 32 lanes of each row (lanes l and l + 32 hold different templates)
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint64_t k = best[r][q];
+#pragma unroll
+        for (int off = 16; off >= 1; off >>= 1) {
+          const uint64_t o = __shfl_xor(k, off, 64);
+          k = o > k ? o : k;
+        }
+        const int m_local = (tblk * RB + r) * 8 + 2 * q + (lane >> 5);
+        if ((lane & 31) == 0 && m_local < n_members) {
+          const int t = a.members[a.m_begin + m_local];
+          if (t >= a.t_begin && t < a.t_end)
+            atomicMax(reinterpret_cast<unsigned long long*>(a.row_max + (t - a.t_begin)), (unsigned long long)k);
+        }
+      }
   }
 }
 
@@ -292,7 +328,7 @@ void gemm_bank_build(const Plan& p, const Group& g, const double2* taps, void* o
 
 namespace {
 
-template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT>
+template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT, bool KEYS>
 void launch_cfg(const GemmArgs& a, hipStream_t stream) {
   const int n_members = a.m_end - a.m_begin;
   constexpr int COLS = window_cols<CT>();
@@ -307,7 +343,7 @@ void launch_cfg(const GemmArgs& a, hipStream_t stream) {
   require(COLS + a.taps + 8 <= 64 * MAXLD, JERK_EINTERNAL, "GEMM window larger than the per-lane load budget");
   require(!RESIDENT || 2 * a.taps / 16 <= KC, JERK_EINTERNAL, "resident tap fragments exceed the register budget");
   const size_t lds = (size_t)2 * (SPLIT ? 4 : 2) * 2 * win_words(COLS, a.taps) * sizeof(uint32_t);
-  hipLaunchKernelGGL((gemm_correlate_kernel<RB, CT, KC, MAXLD, SPLIT, RESIDENT>), dim3((unsigned)blocks), dim3(64), lds, stream, a,
+  hipLaunchKernelGGL((gemm_correlate_kernel<RB, CT, KC, MAXLD, SPLIT, RESIDENT, KEYS>), dim3((unsigned)blocks), dim3(64), lds, stream, a,
                      windows_per_wg, n_colchunks);
 }
 
@@ -323,15 +359,25 @@ void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream) {
   // fragments of 64 taps fit in registers, 1 otherwise.
   const bool two = n_members > 8 && a.taps <= 64;
   // window = 64 outputs + taps + 8 slack elements, loaded 64 per lane-step
-  if (split) {
-    if (two) launch_cfg<2, 2, 8, 3, true, true>(a, stream);
-    else if (a.taps <= 128) launch_cfg<1, 2, 16, 4, true, true>(a, stream);
-    else if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false>(a, stream);
-    else launch_cfg<1, 2, 8, 10, true, false>(a, stream);
+  if (a.row_max) {
+    // peak-key launches keep one row block per wave (room for the per-row keys)
+    if (split) {
+      if (a.taps <= 128) launch_cfg<1, 2, 16, 4, true, true, true>(a, stream);
+      else if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false, true>(a, stream);
+      else launch_cfg<1, 2, 8, 10, true, false, true>(a, stream);
+    } else {
+      if (a.taps <= 256) launch_cfg<1, 2, 32, 6, false, true, true>(a, stream);
+      else launch_cfg<1, 2, 16, 10, false, false, true>(a, stream);
+    }
+  } else if (split) {
+    if (two) launch_cfg<2, 2, 8, 3, true, true, false>(a, stream);
+    else if (a.taps <= 128) launch_cfg<1, 2, 16, 4, true, true, false>(a, stream);
+    else if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false, false>(a, stream);
+    else launch_cfg<1, 2, 8, 10, true, false, false>(a, stream);
   } else {
-    if (two) launch_cfg<2, 2, 8, 3, false, true>(a, stream);
-    else if (a.taps <= 256) launch_cfg<1, 2, 32, 6, false, true>(a, stream);
-    else launch_cfg<1, 2, 16, 10, false, false>(a, stream);
+    if (two) launch_cfg<2, 2, 8, 3, false, true, false>(a, stream);
+    else if (a.taps <= 256) launch_cfg<1, 2, 32, 6, false, true, false>(a, stream);
+    else launch_cfg<1, 2, 16, 10, false, false, false>(a, stream);
   }
   JERK_HIP_CHECK(hipGetLastError());
 }

@@ -79,6 +79,14 @@ bool seg_len_supported(int32_t s);
 
 // templates.hip
 void templates_build(const Plan& p, void* d_bank, hipStream_t stream);
+// Member table + twiddle tables + templates_build (what jerk_templates_build enqueues).
+void bank_build(Plan& p, void* d_bank, hipStream_t stream);
+// FP64 taps [n][2][taps] of templates d_members[0..n) (K = taps, zero outside each template's window).
+void taps_launch(const Plan& p, int32_t taps, const int32_t* d_members, int32_t n, double2* out, hipStream_t stream);
+// FFT-path spectra [n][2][S] of FP64 taps [n][2][K].
+void fft_spectra_launch(const double2* taps, int32_t n, int32_t K, int32_t S, float2* out, hipStream_t stream);
+void gen_twiddles(float2* out, int32_t n, hipStream_t stream);
+void gemm_bank_build(const Plan& p, const Group& g, const double2* taps, void* out, hipStream_t stream);
 
 // fft_correlate.hip. One FFT-path job: one spectrum, one width group, the
 // group's member range [m_begin, m_end), every segment.
@@ -92,8 +100,8 @@ struct FftJob {
   int32_t taps, tpb;
   float* plane;               // plane rows (row stride ld floats), or null
   int64_t ld;
-  uint64_t* row_max;          // peak keys [row][segment] (row stride rmax_ld), or null
-  int64_t rmax_ld;
+  uint64_t* row_max;          // peak keys [row][segment] (row stride rmax_ld), or null;
+  int64_t rmax_ld;            // rmax_ld == 0: one key per row, combined with atomicMax
   int64_t n_seg;              // set by fft_job_tiles
   int64_t tile_begin;         // first tile of the job in a persistent launch
 };
@@ -125,6 +133,7 @@ struct GemmArgs {
   int64_t ld;
   int32_t taps;
   int32_t path;               // JERK_PATH_GEMM_SPLIT_BF16 or JERK_PATH_GEMM_FP16
+  uint64_t* row_max;          // one peak key per row (atomicMax), or null; plane may then be null
 };
 void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream);
 size_t gemm_bank_bytes(int32_t n_members, int32_t taps, int32_t path);
@@ -134,6 +143,19 @@ size_t batch_workspace_bytes(const Plan& p, int32_t count);
 int64_t batch_keys_per_row(const Plan& p, int64_t nbins);
 void batch_search(Plan& p, const void* d_bank, const jerk_batch_item* items, int32_t count, int32_t t_begin,
                   int32_t t_end, void* d_ws, size_t ws_bytes, uint32_t flags, hipStream_t stream);
+
+// tune.cpp
+size_t autotune_scratch_bytes(const Plan& p, int64_t nbins);
+void autotune(Plan& p, const void* d_spec, int64_t nbins, void* d_scratch, size_t scratch_bytes, uint32_t flags,
+              hipStream_t stream);
+
+// serve.cpp
+void serve_create(const jerk_serve_desc& d, void* d_arena, size_t arena_bytes, jerk_server** out);
+void serve_submit(jerk_server& s, const jerk_request& r, uint64_t* ticket);
+int32_t serve_poll(jerk_server& s, uint64_t ticket, jerk_result* out, double timeout_s);
+void serve_stats(jerk_server& s, jerk_serve_stats* out);
+void serve_inject(jerk_server& s, int32_t op, int64_t n);
+void serve_destroy(jerk_server* s);
 
 // reduce.hip
 void peaks_reduce(const uint64_t* keys, int32_t rows, int64_t per_row, int64_t ld, jerk_peak* out,

@@ -129,6 +129,43 @@ void gen_twiddles(float2* out, int32_t n, hipStream_t stream) {
 
 void gemm_bank_build(const Plan& p, const Group& g, const double2* taps, void* out, hipStream_t stream);
 
+void taps_launch(const Plan& p, int32_t taps, const int32_t* d_members, int32_t n, double2* out, hipStream_t stream) {
+  if (n <= 0) return;
+  GlRule gl;
+  for (int k = 0; k < 16; ++k) {
+    gl.x[k] = p.gl_x[k];
+    gl.w[k] = p.gl_w[k];
+  }
+  TapGen a{p.desc.zmax, p.desc.dz, p.desc.dw, p.n_z, p.J, taps, n, d_members, out, p.desc.margin_bins};
+  const int64_t total = (int64_t)n * 2 * taps;
+  hipLaunchKernelGGL(gen_taps_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, a, gl);
+  JERK_HIP_CHECK(hipGetLastError());
+}
+
+void fft_spectra_launch(const double2* taps, int32_t n, int32_t K, int32_t S, float2* out, hipStream_t stream) {
+  if (n <= 0) return;
+  SpecGen s{taps, out, n, K, S};
+  dim3 grid((unsigned)((S + 255) / 256), (unsigned)(2 * n));
+  hipLaunchKernelGGL(gen_fft_spectra_kernel, grid, dim3(256), 0, stream, s);
+  JERK_HIP_CHECK(hipGetLastError());
+}
+
+void bank_build(Plan& p, void* d_bank, hipStream_t stream) {
+  if (!p.pinned_members) {
+    void* h = nullptr;
+    JERK_HIP_CHECK(hipHostMalloc(&h, sizeof(int32_t) * (size_t)p.T, hipHostMallocDefault));
+    p.pinned_members = static_cast<int32_t*>(h);
+    int32_t k = 0;
+    for (const auto& g : p.groups)
+      for (int32_t t : g.members) p.pinned_members[k++] = t;
+  }
+  char* bank = static_cast<char*>(d_bank);
+  JERK_HIP_CHECK(hipMemcpyAsync(bank + p.off_members, p.pinned_members, sizeof(int32_t) * (size_t)p.T,
+                                hipMemcpyHostToDevice, stream));
+  for (int i = 0; i < 4; ++i) gen_twiddles(reinterpret_cast<float2*>(bank + p.off_tw[i]), 512 << i, stream);
+  templates_build(p, d_bank, stream);
+}
+
 void templates_build(const Plan& p, void* d_bank, hipStream_t stream) {
   char* bank = static_cast<char*>(d_bank);
   GlRule gl;
