@@ -5,8 +5,8 @@ A step is one full search of the 2^22-bin spectrum (2^23 float32 samples,
 four seeded tones) over the 201 x 61 = 12261-template lattice (zmax 200,
 wmax 600, dz 2, dw 20) with half-bin r spacing: 1.03e11 plane points. The
 plane (411 GB in FP32) does not fit in HBM, so each step writes it as slabs
-of template rows into one resident slab buffer (every point is written to
-HBM; later slabs overwrite earlier ones). Inputs and the template bank are in
+of up to 476 template rows of one width group into one resident slab buffer
+(every point is written to HBM; later slabs overwrite earlier ones). Inputs and the template bank are in
 HBM before the timed region; template generation is timed separately.
 
 Prints one JSON line (see the keys below). ``--gpus`` above 1 is refused:
@@ -46,12 +46,22 @@ def parse():
     ap.add_argument("--cpu-templates", type=int, default=8,
                     help="templates (full rows) in the oracle's timed sample; 0 skips cpu_baseline")
     ap.add_argument("--errors", type=int, default=1, help="measure plane errors on the 2^15-bin search")
+    ap.add_argument("--autotune", type=int, default=1, help="autotune the plan before timing (untimed)")
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="requests per serving pass (cold then warm template cache); 0 skips serving")
+    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load (arrival rate / service rate)")
+    ap.add_argument("--batch-items", type=int, default=256,
+                    help="spectra in the batched leg (uneven 2^20..2^22 bins); 0 skips it")
+    ap.add_argument("--save-plan", default="", help="write the main plan's per-group configuration (JSON)")
+    ap.add_argument("--load-plan", default="", help="use a saved per-group configuration instead of autotuning")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the main leg, copy a buffer of this size once (HBM counter calibration)")
     return ap.parse_args()
 
 
 def kernel_name(g):
     if g["path"] == 0:
-        return f"fft_correlate_kernel<S={g['seg_len']}>"
+        return f"fft_correlate_kernel<S={g['seg_len']},E={g['fft_ept']}>"
     return "gemm_correlate_kernel<split_bf16>" if g["path"] == 1 else "gemm_correlate_kernel<fp16>"
 
 
@@ -103,28 +113,41 @@ def traffic_from_profiles(kname, launch_points_avg):
 
 
 def run_search_steps(J, torch, plan, bank, spec, slab, rows, steps, timing):
-    """Runs `steps` full searches; records (group, t0, t1, start_event, end_event) when timing."""
-    info = plan.info()
-    T = info["n_templates"]
-    G = info["n_groups"]
+    """Runs `steps` full searches, the plane cut into slabs of up to `rows` members of one width
+    group each (every launch works on whole template blocks); records (group, members, events)."""
+    groups = plan.groups()
     recs = []
     for _ in range(steps):
-        for t0 in range(0, T, rows):
-            t1 = min(T, t0 + rows)
-            for g in range(G):
+        for g, gi in enumerate(groups):
+            for m0 in range(0, gi["n_members"], rows):
+                m1 = min(gi["n_members"], m0 + rows)
                 if timing:
                     e0 = torch.cuda.Event(enable_timing=True)
                     e1 = torch.cuda.Event(enable_timing=True)
                     e0.record()
-                plan.search_group(bank, spec, slab, g, t0, t1)
+                plan.search_members(bank, spec, slab, g, m0, m1)
                 if timing:
                     e1.record()
-                    recs.append((g, t0, t1, e0, e1))
+                    recs.append((g, m1 - m0, e0, e1))
     return recs
 
 
-def time_path(J, torch, spec, n, path, steps, warmup, slab_gb, want_kernels):
+def time_path(J, torch, spec, n, path, steps, warmup, slab_gb, want_kernels, autotune=True, load_plan="",
+              save_plan=""):
     plan = J.Plan(n, 200.0, 600.0, 2.0, 20.0, path=path)
+    t_tune = 0.0
+    if load_plan:
+        cfg = json.load(open(load_plan))
+        for g, c in enumerate(cfg["groups"]):
+            plan.set_group(g, c["seg_len"], c["templates_per_block"], c["path"], c.get("fft_ept", 0))
+    elif autotune and path in ("auto", "fft"):
+        t0 = time.perf_counter()
+        plan.autotune(spec)
+        t_tune = time.perf_counter() - t0
+    if save_plan:
+        json.dump({"workload": "2^22 bins, zmax 200, wmax 600, dz 2, dw 20", "path": path,
+                   "groups": [{k: g[k] for k in ("taps", "seg_len", "templates_per_block", "path", "fft_ept")}
+                              for g in plan.groups()]}, open(save_plan, "w"), indent=1)
     info = plan.info()
     bank = plan.new_bank()
     torch.cuda.synchronize()
@@ -143,17 +166,12 @@ def time_path(J, torch, spec, n, path, steps, warmup, slab_gb, want_kernels):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     groups = plan.groups()
-    members = plan.members()
-    out = {"plan": plan, "wall": wall, "t_build": t_build, "T": T, "rows": rows, "kernels": None,
+    out = {"plan": plan, "wall": wall, "t_build": t_build, "t_tune": t_tune, "T": T, "rows": rows, "kernels": None,
            "groups": groups}
     if want_kernels:
         agg = {}
-        for g, a, b, e0, e1 in recs:
+        for g, m, e0, e1 in recs:
             gi = groups[g]
-            ms = members[gi["first_member"]: gi["first_member"] + gi["n_members"]]
-            m = int(((ms >= a) & (ms < b)).sum())
-            if m == 0:
-                continue
             ms_t = e0.elapsed_time(e1) * 1e-3
             pts, fl, by = launch_counts(gi, m, n)
             k = kernel_name(gi)
@@ -208,6 +226,101 @@ def plane_errors(J, torch):
     return res
 
 
+def serving_leg(J, torch, n_req, load):
+    """Poisson stream of search requests (lengths 2^18..2^23 bins, zmax 50..300, wmax 3 zmax,
+    FP32 / split-BF16 half and half) through the request server, twice: a cold template
+    cache, then the same stream again with every grid's bank resident. Latency is host time
+    from submit to completion."""
+    import numpy as np
+    import synth
+    reqs = synth.serving_requests(n_req, 1.0)
+    # one resident spectrum per length class (seeded), shared by the requests of that length
+    specs = {}
+    for r in reqs:
+        if r["n_samples"] not in specs:
+            x = synth.time_series(r["n_samples"], r["seed"], r["tones"])
+            specs[r["n_samples"]] = torch.from_numpy(synth.spectrum_from_series(x)).cuda()
+    arena = torch.empty(96 << 30, dtype=torch.uint8, device="cuda")
+    srv = J.Server(arena, max_active=4, queue_capacity=4 * n_req, tiles_per_launch=1 << 16)
+
+    def run_pass(rate):
+        t0 = time.perf_counter()
+        tickets = []
+        for r in reqs:
+            due = t0 + r["arrival_s"] / rate
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+                time.sleep(min(0.002, due - now))
+            tickets.append(srv.submit(specs[r["n_samples"]], r["zmax"], r["wmax"], r["dz"], r["dw"],
+                                      path="split_bf16" if r["split_bf16"] else "fft"))
+        res = [srv.wait(t, 600.0) for t in tickets]
+        wall = time.perf_counter() - t0
+        lat = np.array([x["t_done"] - x["t_submit"] for x in res])
+        pts = sum(x["points"] for x in res)
+        ok = all(x["status"] == 0 for x in res)
+        return {"requests": len(res), "ok": ok, "p50_s": float(np.percentile(lat, 50)),
+                "p99_s": float(np.percentile(lat, 99)), "max_s": float(lat.max()), "wall_s": wall,
+                "points_per_s": pts / wall, "points": pts}
+
+    # service rate from the mean request size and a closed-loop pass (cold cache)
+    cold = run_pass(1e9)   # all at once: measures the service capacity with cold banks
+    mu = cold["requests"] / cold["wall_s"]
+    rate = load * mu
+    warm = run_pass(rate)
+    st = srv.stats()
+    srv.close()
+    del arena
+    return {"load": load, "arrival_rate_hz": rate, "cold_closed_loop": cold, "warm_poisson": warm,
+            "bank_builds": st["bank_builds"], "launches": st["launches"],
+            "workload": "synth.serving_requests(seed 191105): lengths 2^18..2^23 bins, zmax even in [50, 300], "
+                        "wmax 3 zmax, dz 2, dw 20, 50% tones, 50% split-BF16; peaks mode"}
+
+
+def batch_leg(J, torch, n_items, slab_rows=128):
+    """256 uneven de-dispersion-trial spectra (2^20, 2^21, 2^22 bins; zmax 100, wmax 300) through
+    jerk_batch_search: one graph-replayed persistent launch per template slab over all spectra.
+    Spectra are N(0,1) noise generated on the GPU (seeded torch generator) and normalised to unit
+    mean power; plane slabs go to a ring of buffers shared by the items (real HBM writes)."""
+    import synth
+    specs_meta = synth.batch_spectra_specs(n_items)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(191103)
+    specs = []
+    for n_samp, seed, tones in specs_meta:
+        x = torch.randn(n_samp, device="cuda", generator=g, dtype=torch.float32)
+        X = torch.fft.rfft(x)[: n_samp // 2]
+        X[0] = 0
+        X = X / torch.sqrt((X[1:].abs() ** 2).mean())
+        specs.append(X.to(torch.complex64).contiguous())
+    nmax = max(s.shape[0] for s in specs)
+    plan = J.Plan(nmax, 100.0, 300.0, 2.0, 20.0, path="fft")
+    t0 = time.perf_counter()
+    plan.autotune(specs[0], uniform=True)
+    t_tune = time.perf_counter() - t0
+    bank = plan.new_bank()
+    plan.build_templates(bank)
+    T = plan.info()["n_templates"]
+    ring = [torch.empty((slab_rows, 2 * nmax), dtype=torch.float32, device="cuda") for _ in range(4)]
+    ws = torch.empty(plan.batch_workspace_bytes(n_items), dtype=torch.uint8, device="cuda")
+    items = [(s, ring[i % len(ring)], None) for i, s in enumerate(specs)]
+    pts = sum(2 * s.shape[0] for s in specs) * T
+    # warm-up (captures the graph), then one timed pass over all slabs
+    plan.batch_search(bank, items, ws, 0, min(T, slab_rows), graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t_b in range(0, T, slab_rows):
+        plan.batch_search(bank, items, ws, t_b, min(T, t_b + slab_rows), graph=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    seg = plan.group(0)["seg_len"]
+    plan.close()
+    return {"items": n_items, "templates": T, "points": pts, "wall_s": wall, "points_per_s": pts / wall,
+            "seg_len": seg, "autotune_s": t_tune, "launches": -(-T // slab_rows),
+            "workload": "synth.batch_spectra_specs(256, seed 191103) lengths; GPU noise spectra; zmax 100, wmax 300"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -230,7 +343,15 @@ def main():
     spec = torch.from_numpy(spec_np).cuda()
     print(f"[bench] spectrum {n} bins ready; path {args.path}", file=sys.stderr, flush=True)
 
-    main_res = time_path(J, torch, spec, n, args.path, args.steps, args.warmup, args.slab_gb, True)
+    main_res = time_path(J, torch, spec, n, args.path, args.steps, args.warmup, args.slab_gb, True,
+                         autotune=bool(args.autotune), load_plan=args.load_plan, save_plan=args.save_plan)
+    if args.calib_copy_mib > 0:
+        a = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     T = main_res["T"]
     points_per_step = 2 * n * T
     wall = main_res["wall"]
@@ -259,7 +380,8 @@ def main():
     roof["hbm_frac"] = roof["hbm_GBps"] / HBM_PEAK_GBS
     roof["avg_launch_ms"] = avg_t * 1e3
     roof["launches"] = d["launches"]
-    kernels_out = {k: {"launches": v["launches"], "time_s": v["time"], "points_per_s": v["points"] / v["time"],
+    kernels_out = {k: {"launches": v["launches"], "time_s": v["time"], "points": v["points"],
+                       "avg_launch_us": v["time"] / v["launches"] * 1e6, "points_per_s": v["points"] / v["time"],
                        "tflops": v["flops"] / v["time"] / 1e12, "hbm_GBps": v["bytes"] / v["time"] / 1e9}
                    for k, v in ks.items()}
 
@@ -268,16 +390,26 @@ def main():
         for p in ("fft", "split_bf16"):
             if p == args.path:
                 continue
-            r = time_path(J, torch, spec, n, p, max(1, args.steps // 2), 1, args.slab_gb, False)
+            r = time_path(J, torch, spec, n, p, max(1, args.steps // 2), 1, args.slab_gb, False,
+                          autotune=bool(args.autotune))
             paths[p] = points_per_step * max(1, args.steps // 2) / r["wall"]
             print(f"[bench] {p}: {paths[p]:.3e} points/s", file=sys.stderr, flush=True)
             r["plan"].close()
 
     errors = plane_errors(J, torch) if args.errors else None
+    serving = None
+    if args.serve_requests > 0:
+        serving = serving_leg(J, torch, args.serve_requests, args.serve_load)
+        print(f"[bench] serving warm p50 {serving['warm_poisson']['p50_s']:.3f} s p99 "
+              f"{serving['warm_poisson']['p99_s']:.3f} s", file=sys.stderr, flush=True)
+    batch = None
+    if args.batch_items > 0:
+        batch = batch_leg(J, torch, args.batch_items)
+        print(f"[bench] batch {batch['points_per_s']:.3e} points/s", file=sys.stderr, flush=True)
     cpu = cpu_baseline(spec_np, args.cpu_templates) if args.cpu_templates > 0 else None
 
     line = {
-        "metric": "(r,z,w) plane points/s",
+        "metric": "(r,z,w) plane points/s, FP32 vs split-BF16 @<=1e-4 rel err; p50/p99 latency",
         "value": value,
         "unit": "points/s",
         "n_gpus": 1,
@@ -291,14 +423,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single search, 2^22 bins (2^23 float32 samples, 4 seeded tones), "
                                "zmax 200, wmax 600, dz 2, dw 20 (201x61=12261 templates), half-bin r, "
-                               f"path {args.path}, plane written as {main_res['rows']}-row slabs",
+                               f"path {args.path}, plane written as slabs of up to {main_res['rows']} rows "
+                               "of one width group",
                    "nbins": n, "templates": T, "points_per_step": points_per_step},
         "roofline": roof,
         "cpu_baseline": cpu,
         "paths_points_per_s": paths,
         "plane_error_2e15_bins": errors,
         "template_build_s": main_res["t_build"],
+        "autotune_s": main_res["t_tune"],
         "kernels": kernels_out,
+        "serving": serving,
+        "batched_256_spectra": batch,
     }
     print(json.dumps(line))
 

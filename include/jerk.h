@@ -106,6 +106,8 @@ typedef struct jerk_group_info_t {
   int32_t path;                /* resolved path (FFT_FP32, GEMM_SPLIT_BF16 or GEMM_FP16) */
   int32_t n_members;           /* templates in the group                                */
   int32_t first_member;        /* index of its first entry in jerk_plan_members order   */
+  int32_t fft_ept;             /* FFT kernel variant: complex elements per thread (8 or 16) */
+  int32_t reserved;
   size_t taps_offset;          /* bank byte offset of the group's FP64 taps:
                                   complex128 [n_members][2 phases][taps], tap j multiplies
                                   bin k0 - taps/2 + 1 + j; taps outside the template's own
@@ -123,10 +125,11 @@ int32_t jerk_plan_template(const jerk_plan* plan, int32_t t, double* zbar, doubl
                            int32_t* half_width, int32_t* group, int32_t* slot);
 /* Template indices of all groups, group by group (n_templates int32, host memory). */
 int32_t jerk_plan_members(const jerk_plan* plan, int32_t* out, int32_t count);
-/* Overrides one group's FFT segment length, templates per block and path before
- * jerk_templates_build (used by the autotuner). Changes bank_bytes; EINVAL if out of range. */
+/* Overrides one group's FFT segment length, templates per block, path and FFT kernel variant
+ * (fft_ept: complex elements per thread, 8 or 16; 0 = default) before jerk_templates_build
+ * (used by the autotuner). Changes bank_bytes; EINVAL if out of range. */
 int32_t jerk_plan_set_group(jerk_plan* plan, int32_t g, int32_t seg_len,
-                            int32_t templates_per_block, int32_t path);
+                            int32_t templates_per_block, int32_t path, int32_t fft_ept);
 
 /* ---- autotuner -------------------------------------------------------------- */
 #define JERK_TUNE_UNIFORM 1u /* one FFT segment length for all groups (for jerk_batch_search) */
@@ -169,13 +172,21 @@ int32_t jerk_search_group(const jerk_plan* plan, const void* d_bank, const void*
                           float* d_plane, int64_t ld, int32_t t_begin, int32_t t_end, int32_t g,
                           hipStream_t stream);
 
+/* As jerk_search_group for members [m_begin, m_end) of group g's member list (jerk_plan_members
+ * order), with output row (member - m_begin): d_plane + (member - m_begin) * ld. Lets a caller cut
+ * the plane into slabs of whole width groups, so every launch works on full template blocks. */
+int32_t jerk_search_members(const jerk_plan* plan, const void* d_bank, const void* d_spec, int64_t nbins,
+                            float* d_plane, int64_t ld, int32_t g, int32_t m_begin, int32_t m_end,
+                            hipStream_t stream);
+
 /* ---- batched search: many spectra, one persistent launch -------------------- */
 typedef struct jerk_batch_item {
   const void* spec;  /* device complex64 spectrum [nbins]                                 */
   int64_t nbins;     /* >= 1; items may have different lengths                          */
   float* plane;      /* device plane rows [t_begin, t_end) x 2 nbins (row stride ld), or NULL */
   int64_t ld;        /* even, >= 2 nbins when plane is set                              */
-  uint64_t* peaks;   /* device peak keys [t_end - t_begin][keys_ld], or NULL (see below)  */
+  uint64_t* peaks;   /* device peak keys [t_end - t_begin][keys_ld], or NULL (see below); either
+                        every item of a batch has one or none has                          */
   int64_t keys_ld;   /* >= jerk_batch_keys_per_row(plan, nbins) when peaks is set        */
 } jerk_batch_item;
 

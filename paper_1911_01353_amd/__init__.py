@@ -100,10 +100,10 @@ class Plan:
         _lib.check(_lib.load().jerk_plan_members(self.handle, out.ctypes.data_as(C.POINTER(C.c_int32)), n))
         return out
 
-    def set_group(self, g: int, seg_len: int, templates_per_block: int, path) -> None:
+    def set_group(self, g: int, seg_len: int, templates_per_block: int, path, ept: int = 0) -> None:
         if isinstance(path, str):
             path = PATH_NAMES[path]
-        _lib.check(_lib.load().jerk_plan_set_group(self.handle, g, seg_len, templates_per_block, path))
+        _lib.check(_lib.load().jerk_plan_set_group(self.handle, g, seg_len, templates_per_block, path, ept))
 
     # -- device work ------------------------------------------------------------
     def new_bank(self, device="cuda"):
@@ -156,6 +156,14 @@ class Plan:
         _lib.check(_lib.load().jerk_plan_autotune(self.handle, _dev_ptr(spec), n, _dev_ptr(scratch), nbytes,
                                                   _lib.TUNE_UNIFORM if uniform else 0, _stream_ptr(stream)))
         del scratch
+
+    def search_members(self, bank, spec, plane, g: int, m_begin: int, m_end: int, stream=None) -> None:
+        """Enqueue ``jerk_search_members``: members [m_begin, m_end) of group g, row = member - m_begin."""
+        n = spec.shape[0]
+        if plane.shape[0] < m_end - m_begin or plane.shape[1] < 2 * n or plane.stride(1) != 1:
+            raise ValueError("plane too small for the requested rows")
+        _lib.check(_lib.load().jerk_search_members(self.handle, _dev_ptr(bank), _dev_ptr(spec), n, _dev_ptr(plane),
+                                                   plane.stride(0), g, m_begin, m_end, _stream_ptr(stream)))
 
     # -- batched search -----------------------------------------------------------
     def batch_workspace_bytes(self, count: int) -> int:

@@ -55,7 +55,7 @@ class GroupInfo(C.Structure):
     _fields_ = [
         ("taps", C.c_int32), ("seg_len", C.c_int32), ("templates_per_block", C.c_int32),
         ("path", C.c_int32), ("n_members", C.c_int32), ("first_member", C.c_int32),
-        ("taps_offset", C.c_size_t),
+        ("fft_ept", C.c_int32), ("reserved", C.c_int32), ("taps_offset", C.c_size_t),
     ]
 
 
@@ -117,12 +117,14 @@ SIGNATURES = {
     "jerk_plan_template": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "jerk_plan_members": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32]),
-    "jerk_plan_set_group": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "jerk_plan_set_group": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "jerk_templates_build": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "jerk_search": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                 C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "jerk_search_group": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                       C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
+    "jerk_search_members": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                        C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
     "jerk_batch_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int32]),
     "jerk_batch_keys_per_row": (C.c_int64, [C.c_void_p, C.c_int64]),
     "jerk_batch_search": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(BatchItem), C.c_int32, C.c_int32, C.c_int32,

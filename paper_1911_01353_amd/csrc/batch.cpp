@@ -24,8 +24,9 @@ struct BatchCtx {
   hipGraphExec_t exec = nullptr;
   const void* graph_ws = nullptr;
   const void* graph_tw = nullptr;
-  int32_t graph_seg = 0, graph_grid = 0;
-  int32_t grid_cache_seg = 0, grid_cache = 0;
+  int32_t graph_seg = 0, graph_ept = 0, graph_grid = 0;
+  bool graph_keys = false;
+  int32_t grid_cache_seg = 0, grid_cache_ept = 0, grid_cache = 0;
 };
 
 void batch_ctx_free(BatchCtx* c) {
@@ -48,16 +49,19 @@ size_t jobs_capacity_bytes(const Plan& p, int32_t count) {
   return kHeaderBytes + align_up((size_t)count * p.groups.size() * sizeof(FftJob));
 }
 
-int32_t uniform_seg_len(const Plan& p) {
-  int32_t s = 0;
+// The one (segment length, elements per thread) FFT variant of all groups.
+std::pair<int32_t, int32_t> uniform_variant(const Plan& p) {
+  int32_t s = 0, e = 0;
   for (const Group& g : p.groups) {
     require(g.path == JERK_PATH_FFT_FP32, JERK_EINVAL,
             "batched search runs the FFT path: every width group must use JERK_PATH_FFT_FP32");
-    require(s == 0 || s == g.seg_len, JERK_EINVAL,
-            "batched search needs one FFT segment length for all width groups (plan seg_len or autotuner)");
+    require(s == 0 || (s == g.seg_len && e == g.ept), JERK_EINVAL,
+            "batched search needs one FFT segment length and kernel variant for all width groups "
+            "(plan seg_len or the autotuner's uniform mode)");
     s = g.seg_len;
+    e = g.ept;
   }
-  return s;
+  return {s, e};
 }
 
 }  // namespace
@@ -79,7 +83,8 @@ void batch_search(Plan& p, const void* d_bank, const jerk_batch_item* items, int
   require(count >= 0 && (count == 0 || items != nullptr), JERK_EINVAL, "items must not be NULL");
   require(0 <= t_begin && t_begin <= t_end && t_end <= p.T, JERK_EINVAL, "template range outside [0, n_templates]");
   require((flags & ~JERK_BATCH_GRAPH) == 0, JERK_EINVAL, "unknown flags");
-  const int32_t seg = uniform_seg_len(p);
+  const auto var = uniform_variant(p);
+  const int32_t seg = var.first, ept = var.second;
   const size_t need = jobs_capacity_bytes(p, count);
   require(d_ws != nullptr && ws_bytes >= need, JERK_ENOMEM, "workspace smaller than jerk_batch_workspace_bytes");
   require(reinterpret_cast<uintptr_t>(d_ws) % 256 == 0, JERK_EINVAL, "workspace must be 256-byte aligned");
@@ -94,6 +99,12 @@ void batch_search(Plan& p, const void* d_bank, const jerk_batch_item* items, int
             JERK_EINVAL, "item buffers must be 8-byte aligned");
   }
 
+  bool keys = false;
+  for (int32_t i = 0; i < count; ++i) {
+    require(i == 0 || (items[i].peaks != nullptr) == keys, JERK_EINVAL,
+            "either every item of a batch has a peak buffer or none has");
+    keys = items[i].peaks != nullptr;
+  }
   const char* bank = static_cast<const char*>(d_bank);
   const int32_t* members = reinterpret_cast<const int32_t*>(bank + p.off_members);
   std::vector<FftJob> jobs;
@@ -139,9 +150,10 @@ void batch_search(Plan& p, const void* d_bank, const jerk_batch_item* items, int
     JERK_HIP_CHECK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
   }
   require(c.device == dev, JERK_EINVAL, "a plan's batched launches must stay on one device");
-  if (c.grid_cache_seg != seg) {
-    c.grid_cache = fft_persistent_grid(seg);
+  if (c.grid_cache_seg != seg || c.grid_cache_ept != ept) {
+    c.grid_cache = fft_persistent_grid(seg, ept);
     c.grid_cache_seg = seg;
+    c.grid_cache_ept = ept;
   }
   const int32_t grid = (int32_t)std::min<int64_t>(c.grid_cache, total);
 
@@ -170,20 +182,21 @@ void batch_search(Plan& p, const void* d_bank, const jerk_batch_item* items, int
   if (!(flags & JERK_BATCH_GRAPH)) {
     JERK_HIP_CHECK(hipMemcpyAsync(ws, c.pinned, bytes, hipMemcpyHostToDevice, stream));
     JERK_HIP_CHECK(hipEventRecord(c.staged, stream));
-    fft_persistent_launch(d_jobs, d_hdr, seg, tw, grid, stream);
+    fft_persistent_launch(d_jobs, d_hdr, seg, ept, keys, tw, grid, stream);
     return;
   }
   // Graph path: the graph holds the counter reset and the persistent kernel;
   // its arguments (workspace, twiddles, grid) fix the graph, the job table does not.
   const int32_t ggrid = c.grid_cache;  // full-size grid so one graph serves any tile count
-  if (!c.exec || c.graph_ws != d_ws || c.graph_tw != tw || c.graph_seg != seg || c.graph_grid != ggrid) {
+  if (!c.exec || c.graph_ws != d_ws || c.graph_tw != tw || c.graph_seg != seg || c.graph_ept != ept ||
+      c.graph_grid != ggrid || c.graph_keys != keys) {
     if (c.exec) JERK_HIP_CHECK(hipGraphExecDestroy(c.exec));
     if (c.graph) JERK_HIP_CHECK(hipGraphDestroy(c.graph));
     c.exec = nullptr;
     c.graph = nullptr;
     JERK_HIP_CHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
     try {
-      fft_persistent_launch(d_jobs, d_hdr, seg, tw, ggrid, c.stream);
+      fft_persistent_launch(d_jobs, d_hdr, seg, ept, keys, tw, ggrid, c.stream);
     } catch (...) {
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(c.stream, &g);
@@ -195,6 +208,8 @@ void batch_search(Plan& p, const void* d_bank, const jerk_batch_item* items, int
     c.graph_ws = d_ws;
     c.graph_tw = tw;
     c.graph_seg = seg;
+    c.graph_ept = ept;
+    c.graph_keys = keys;
     c.graph_grid = ggrid;
   }
   JERK_HIP_CHECK(hipEventRecord(c.ev_in, stream));

@@ -67,7 +67,8 @@ void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64
       j.ld = ld;
       j.taps = g.taps;
       j.tpb = g.tpb;
-      fft_correlate_launch(j, g.seg_len, reinterpret_cast<const float2*>(bank + p.off_tw[tw_slot(g.seg_len)]), stream);
+      fft_correlate_launch(j, g.seg_len, g.ept, reinterpret_cast<const float2*>(bank + p.off_tw[tw_slot(g.seg_len)]),
+                           stream);
     } else {
       GemmArgs a{};
       a.spec = static_cast<const float2*>(d_spec);
@@ -84,6 +85,49 @@ void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64
       a.path = g.path;
       gemm_correlate_launch(a, stream);
     }
+  }
+}
+
+// Rows [m_begin, m_end) of group g's member list, output row = member - m_begin.
+void search_members_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64_t nbins, float* d_plane,
+                            int64_t ld, int32_t gi, int32_t m_begin, int32_t m_end, hipStream_t stream) {
+  const char* bank = static_cast<const char*>(d_bank);
+  const int32_t* members = reinterpret_cast<const int32_t*>(bank + p.off_members);
+  const Group& g = p.groups[gi];
+  if (g.path == JERK_PATH_FFT_FP32) {
+    FftJob j{};
+    j.spec = static_cast<const float2*>(d_spec);
+    j.nbins = nbins;
+    j.bank_fft = reinterpret_cast<const float2*>(bank + g.off_fft);
+    j.members = members + g.first_member;
+    j.m_begin = m_begin;
+    j.m_end = m_end;
+    j.row_by_member = 1;
+    j.row_base = m_begin;
+    j.plane = d_plane;
+    j.ld = ld;
+    j.taps = g.taps;
+    j.tpb = g.tpb;
+    fft_correlate_launch(j, g.seg_len, g.ept, reinterpret_cast<const float2*>(bank + p.off_tw[tw_slot(g.seg_len)]),
+                         stream);
+  } else {
+    GemmArgs a{};
+    a.spec = static_cast<const float2*>(d_spec);
+    a.nbins = nbins;
+    a.bank_gemm = bank + g.off_gemm;
+    a.members = members + g.first_member;
+    a.m_begin = m_begin / 8 * 8;
+    a.m_end = m_end;
+    a.t_begin = 0;
+    a.t_end = p.T;
+    a.row_by_member = 1;
+    a.row_base = m_begin;
+    a.plane = d_plane;
+    a.ld = ld;
+    a.taps = g.taps;
+    a.path = g.path;
+    // members below m_begin (in the first block of 8) are computed but not written (row < 0)
+    gemm_correlate_launch(a, stream);
   }
 }
 
@@ -171,6 +215,7 @@ int32_t jerk_plan_group(const jerk_plan* plan, int32_t g, jerk_group_info_t* out
     out->n_members = (int32_t)G.members.size();
     out->first_member = G.first_member;
     out->taps_offset = G.off_taps;
+    out->fft_ept = G.ept;
   });
 }
 
@@ -199,7 +244,7 @@ int32_t jerk_plan_members(const jerk_plan* plan, int32_t* out, int32_t count) {
 }
 
 int32_t jerk_plan_set_group(jerk_plan* plan, int32_t g, int32_t seg_len, int32_t templates_per_block,
-                            int32_t path) {
+                            int32_t path, int32_t fft_ept) {
   return guarded([&] {
     require(plan != nullptr, JERK_EINVAL, "plan must not be NULL");
     jerk::Plan& p = plan->p;
@@ -213,9 +258,13 @@ int32_t jerk_plan_set_group(jerk_plan* plan, int32_t g, int32_t seg_len, int32_t
             JERK_EINVAL, "group path must be FFT_FP32, GEMM_SPLIT_BF16 or GEMM_FP16");
     require(path == JERK_PATH_FFT_FP32 || G.taps <= 512, JERK_EUNSUPPORTED,
             "MFMA paths support templates up to 512 taps");
+    if (fft_ept == 0) fft_ept = seg_len == 512 ? 8 : 16;
+    require(jerk::fft_variant_supported(seg_len, fft_ept), JERK_EINVAL,
+            "no FFT kernel variant with this segment length and elements per thread");
     G.seg_len = seg_len;
     G.tpb = templates_per_block;
     G.path = path;
+    G.ept = fft_ept;
     jerk::plan_layout(p);
   });
 }
@@ -362,6 +411,24 @@ int32_t jerk_serve_inject_failure(jerk_server* srv, int32_t op, int64_t n) {
 int32_t jerk_serve_destroy(jerk_server* srv) {
   return guarded([&] {
     if (srv) jerk::serve_destroy(srv);
+  });
+}
+
+int32_t jerk_search_members(const jerk_plan* plan, const void* d_bank, const void* d_spec, int64_t nbins,
+                            float* d_plane, int64_t ld, int32_t g, int32_t m_begin, int32_t m_end, hipStream_t stream) {
+  return guarded([&] {
+    require(plan != nullptr, JERK_EINVAL, "plan must not be NULL");
+    const jerk::Plan& p = plan->p;
+    require(g >= 0 && g < (int32_t)p.groups.size(), JERK_EINVAL, "group index out of range");
+    const int32_t n = (int32_t)p.groups[g].members.size();
+    require(0 <= m_begin && m_begin <= m_end && m_end <= n, JERK_EINVAL, "member range outside the group");
+    if (m_begin == m_end) return;
+    require(d_bank && d_spec && d_plane, JERK_EINVAL, "bank, spectrum and plane must not be NULL");
+    require(nbins >= 1, JERK_EINVAL, "nbins must be >= 1");
+    require(ld >= 2 * nbins && ld % 2 == 0, JERK_EINVAL, "ld must be even and >= 2 * nbins");
+    require(reinterpret_cast<uintptr_t>(d_plane) % 8 == 0 && reinterpret_cast<uintptr_t>(d_spec) % 8 == 0,
+            JERK_EINVAL, "spectrum and plane must be 8-byte aligned");
+    jerk::search_members_enqueue(p, d_bank, d_spec, nbins, d_plane, ld, g, m_begin, m_end, stream);
   });
 }
 

@@ -155,6 +155,7 @@ __device__ __forceinline__ uint64_t block_max_key(uint64_t k, uint64_t* red) {
     k = o > k ? o : k;
   }
   if constexpr (TPB > 64) {
+    static_assert(TPB <= 512, "reduction buffer holds 8 waves");
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) red[wave] = k;
     __syncthreads();
@@ -172,17 +173,20 @@ __device__ __forceinline__ uint64_t peak_key(float power, int64_t p) {
 
 // One tile: segment `seg` of job `j` against template block `tb` (up to j.tpb
 // templates of the job's member range). Writes the plane rows and/or the
-// per-(row, segment) peak keys.
-template <int S, int E, int R1, int R2, int R3>
+// per-(row, segment) peak keys. Radices R1..R4 (R4 = 1: three passes) run
+// forward in that order and inverse in the reverse order.
+template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS>
 __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int tb, float2* lds, uint64_t* red,
                                          const float2* __restrict__ tw) {
   constexpr int TPB = S / E;
+  constexpr bool P4 = R4 > 1;
+  constexpr int RL = P4 ? R4 : R3;  // last forward radix = first inverse radix
   const int tid = threadIdx.x;
   const int K = j.taps;
   const int U = S - K + 1;
   const int64_t base = seg * U - (K / 2 - 1);
 
-  // ---- forward FFT of the segment (radices R1, R2, R3) ----
+  // ---- forward FFT of the segment ----
   float2 v[E];
   {
     constexpr int M = E / R1;
@@ -198,7 +202,12 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int tb, f
   }
   stockham_pass<S, E, R1, 1, false, false, true>(v, lds, tw, tid);
   stockham_pass<S, E, R2, R1, false, true, true>(v, lds, tw, tid);
-  stockham_pass<S, E, R3, R1 * R2, false, true, false>(v, lds, tw, tid);
+  if constexpr (P4) {
+    stockham_pass<S, E, R3, R1 * R2, false, true, true>(v, lds, tw, tid);
+    stockham_pass<S, E, R4, R1 * R2 * R3, false, true, false>(v, lds, tw, tid);
+  } else {
+    stockham_pass<S, E, R3, R1 * R2, false, true, false>(v, lds, tw, tid);
+  }
   float2 F[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) F[e] = v[e];
@@ -210,30 +219,37 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int tb, f
   const int lag_lim = (int)min((int64_t)U, j.nbins - seg * U);
   for (int mm = m0; mm < m1; ++mm) {
     const int t = j.members[mm];
-    const int64_t row = t - j.t_begin;
+    const int64_t row = j.row_by_member ? (int64_t)(mm - j.row_base) : (int64_t)(t - j.t_begin);
     float P0[E];
 #pragma unroll
     for (int phase = 0; phase < 2; ++phase) {
       const float2* __restrict__ H = j.bank_fft + ((int64_t)mm * 2 + phase) * S;
       {
-        constexpr int M = E / R3;
+        constexpr int M = E / RL;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
           const unsigned b = tid + m * TPB;
 #pragma unroll
-          for (int k = 0; k < R3; ++k) v[m * R3 + k] = cmul(F[m * R3 + k], H[b + k * (S / R3)]);
+          for (int k = 0; k < RL; ++k) v[m * RL + k] = cmul(F[m * RL + k], H[b + k * (S / RL)]);
         }
       }
-      stockham_pass<S, E, R3, 1, true, false, true>(v, lds, tw, tid);
-      stockham_pass<S, E, R2, R3, true, true, true>(v, lds, tw, tid);
-      stockham_pass<S, E, R1, R3 * R2, true, true, false>(v, lds, tw, tid);
+      if constexpr (P4) {
+        stockham_pass<S, E, R4, 1, true, false, true>(v, lds, tw, tid);
+        stockham_pass<S, E, R3, R4, true, true, true>(v, lds, tw, tid);
+        stockham_pass<S, E, R2, R4 * R3, true, true, true>(v, lds, tw, tid);
+        stockham_pass<S, E, R1, R4 * R3 * R2, true, true, false>(v, lds, tw, tid);
+      } else {
+        stockham_pass<S, E, R3, 1, true, false, true>(v, lds, tw, tid);
+        stockham_pass<S, E, R2, R3, true, true, true>(v, lds, tw, tid);
+        stockham_pass<S, E, R1, R3 * R2, true, true, false>(v, lds, tw, tid);
+      }
       // thread holds lag b + k S/R1 in v[m R1 + k]
       if (phase == 0) {
 #pragma unroll
         for (int e = 0; e < E; ++e) P0[e] = fmaf(v[e].x, v[e].x, v[e].y * v[e].y);
       } else {
         constexpr int M = E / R1;
-        uint64_t best = 0;
+        [[maybe_unused]] uint64_t best = 0;
         // uniform row base; lanes add 32-bit offsets
         float2* __restrict__ out2 =
             j.plane ? reinterpret_cast<float2*>(j.plane + row * j.ld) + seg * U : nullptr;
@@ -248,7 +264,7 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int tb, f
               const float p0 = P0[m * R1 + k];
               const float p1 = fmaf(vv.x, vv.x, vv.y * vv.y);
               if (out2) out2[(unsigned)lag] = make_float2(p0, p1);
-              if (j.row_max) {
+              if constexpr (KEYS) {
                 const int64_t p = 2 * (seg * U + lag);
                 const uint64_t k0 = peak_key(p0, p), k1 = peak_key(p1, p + 1);
                 const uint64_t kk = k1 > k0 ? k1 : k0;
@@ -257,7 +273,7 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int tb, f
             }
           }
         }
-        if (j.row_max) {
+        if constexpr (KEYS) {
           best = block_max_key<TPB>(best, red);
           if (tid == 0) {
             if (j.rmax_ld == 0) atomicMax(reinterpret_cast<unsigned long long*>(j.row_max + row), (unsigned long long)best);
@@ -269,26 +285,27 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int tb, f
   }
 }
 
-// One job, one workgroup per tile: blockIdx = tb * n_seg + seg.
-template <int S, int E, int R1, int R2, int R3>
+// One job, one workgroup per tile: blockIdx = tb * n_seg + seg. KEYS: write
+// peak keys (j.row_max) as well as (or instead of) the plane.
+template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS>
 __global__ void __launch_bounds__(S / E) fft_correlate_kernel(FftJob j, const float2* __restrict__ tw) {
-  static_assert(R1 * R2 * R3 == S, "radices must multiply to S");
+  static_assert(R1 * R2 * R3 * R4 == S, "radices must multiply to S");
   __shared__ float2 lds[S + S / 16];
-  __shared__ uint64_t red[4];
+  __shared__ uint64_t red[8];
   const int64_t blk = blockIdx.x;
-  fft_tile<S, E, R1, R2, R3>(j, blk % j.n_seg, (int)(blk / j.n_seg), lds, red, tw);
+  fft_tile<S, E, R1, R2, R3, R4, KEYS>(j, blk % j.n_seg, (int)(blk / j.n_seg), lds, red, tw);
 }
 
 // Persistent launch over a job table: every workgroup takes tiles from a
 // device counter until all tiles of all jobs are done (every workgroup
 // reaches the exit test). Tile i belongs to the job whose [tile_begin,
 // next tile_begin) holds it; within a job, tile = tb * n_seg + seg.
-template <int S, int E, int R1, int R2, int R3>
+template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS>
 __global__ void __launch_bounds__(S / E) fft_persistent_kernel(const FftJob* __restrict__ jobs,
                                                                BatchHeader* __restrict__ hdr,
                                                                const float2* __restrict__ tw) {
   __shared__ float2 lds[S + S / 16];
-  __shared__ uint64_t red[4];
+  __shared__ uint64_t red[8];
   __shared__ int64_t s_tile;
   const int64_t total = hdr->total_tiles;
   const int n_jobs = hdr->n_jobs;
@@ -306,7 +323,12 @@ __global__ void __launch_bounds__(S / E) fft_persistent_kernel(const FftJob* __r
     }
     const FftJob& j = jobs[lo];
     const int64_t local = tile - j.tile_begin;
-    fft_tile<S, E, R1, R2, R3>(j, local % j.n_seg, (int)(local / j.n_seg), lds, red, tw);
+    // An opaque copy of the twiddle pointer per tile: otherwise the compiler
+    // hoists the twiddle loads out of the tile loop and keeps them live across
+    // tiles, which costs more registers (and waves) than reloading them.
+    const float2* twt = tw;
+    asm volatile("" : "+s"(twt));
+    fft_tile<S, E, R1, R2, R3, R4, KEYS>(j, local % j.n_seg, (int)(local / j.n_seg), lds, red, twt);
   }
 }
 
@@ -324,84 +346,82 @@ int64_t fft_job_tiles(FftJob& j, int32_t seg_len) {
   return j.n_seg * n_tb;
 }
 
-void fft_correlate_launch(FftJob j, int32_t seg_len, const float2* twiddles, hipStream_t stream) {
+// Kernel variants: segment length x elements per thread (16: three radix-16
+// passes where possible; 8: radix-8 passes, one more LDS exchange, about half
+// the registers and twice the waves per SIMD).
+#define JERK_FFT_VARIANTS(X)              \
+  X(512, 8, 8, 8, 8, 1)                   \
+  X(1024, 16, 4, 16, 16, 1)               \
+  X(1024, 8, 2, 8, 8, 8)                  \
+  X(2048, 16, 8, 16, 16, 1)               \
+  X(2048, 8, 4, 8, 8, 8)                  \
+  X(4096, 16, 16, 16, 16, 1)              \
+  X(4096, 8, 8, 8, 8, 8)
+
+bool fft_variant_supported(int32_t seg_len, int32_t ept) {
+#define X(S, E, A, B, C, D) \
+  if (seg_len == S && ept == E) return true;
+  JERK_FFT_VARIANTS(X)
+#undef X
+  return false;
+}
+
+void fft_correlate_launch(FftJob j, int32_t seg_len, int32_t ept, const float2* twiddles, hipStream_t stream) {
   if (j.m_end <= j.m_begin || j.nbins <= 0) return;
   const int64_t blocks = fft_job_tiles(j, seg_len);
   require(blocks < (1ll << 31), JERK_EINVAL, "search too large for one launch; split the template range");
-  switch (seg_len) {
-    case 4096:
-      hipLaunchKernelGGL((fft_correlate_kernel<4096, 16, 16, 16, 16>), dim3((unsigned)blocks), dim3(256), 0, stream, j,
-                         twiddles);
-      break;
-    case 2048:
-      hipLaunchKernelGGL((fft_correlate_kernel<2048, 16, 8, 16, 16>), dim3((unsigned)blocks), dim3(128), 0, stream, j,
-                         twiddles);
-      break;
-    case 1024:
-      hipLaunchKernelGGL((fft_correlate_kernel<1024, 16, 4, 16, 16>), dim3((unsigned)blocks), dim3(64), 0, stream, j,
-                         twiddles);
-      break;
-    case 512:
-      hipLaunchKernelGGL((fft_correlate_kernel<512, 8, 8, 8, 8>), dim3((unsigned)blocks), dim3(64), 0, stream, j,
-                         twiddles);
-      break;
-    default:
-      throw Error(JERK_EINTERNAL, "unsupported segment length");
+  const bool keys = j.row_max != nullptr;
+#define X(S, E, A, B, C, D)                                                                                       \
+  if (seg_len == S && ept == E) {                                                                                 \
+    if (keys)                                                                                                     \
+      hipLaunchKernelGGL((fft_correlate_kernel<S, E, A, B, C, D, true>), dim3((unsigned)blocks), dim3(S / E), 0,  \
+                         stream, j, twiddles);                                                                    \
+    else                                                                                                          \
+      hipLaunchKernelGGL((fft_correlate_kernel<S, E, A, B, C, D, false>), dim3((unsigned)blocks), dim3(S / E), 0, \
+                         stream, j, twiddles);                                                                    \
+    JERK_HIP_CHECK(hipGetLastError());                                                                            \
+    return;                                                                                                       \
   }
-  JERK_HIP_CHECK(hipGetLastError());
+  JERK_FFT_VARIANTS(X)
+#undef X
+  throw Error(JERK_EINTERNAL, "unsupported FFT kernel variant");
 }
 
-int32_t fft_persistent_grid(int32_t seg_len) {
-  int dev = 0, cus = 0, per_cu = 0;
+int32_t fft_persistent_grid(int32_t seg_len, int32_t ept) {
+  int dev = 0, cus = 0, per_cu = 0, per_cu_k = 0;
   JERK_HIP_CHECK(hipGetDevice(&dev));
   JERK_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  switch (seg_len) {
-    case 4096:
-      JERK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(fft_persistent_kernel<4096, 16, 16, 16, 16>), 256, 0));
-      break;
-    case 2048:
-      JERK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(fft_persistent_kernel<2048, 16, 8, 16, 16>), 128, 0));
-      break;
-    case 1024:
-      JERK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(fft_persistent_kernel<1024, 16, 4, 16, 16>), 64, 0));
-      break;
-    case 512:
-      JERK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(fft_persistent_kernel<512, 8, 8, 8, 8>), 64, 0));
-      break;
-    default:
-      throw Error(JERK_EINTERNAL, "unsupported segment length");
+#define X(S, E, A, B, C, D)                                                                                 \
+  if (seg_len == S && ept == E) {                                                                           \
+    JERK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(                                            \
+        &per_cu, reinterpret_cast<const void*>(fft_persistent_kernel<S, E, A, B, C, D, false>), S / E, 0)); \
+    JERK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(                                            \
+        &per_cu_k, reinterpret_cast<const void*>(fft_persistent_kernel<S, E, A, B, C, D, true>), S / E, 0)); \
   }
-  return std::max(1, cus) * std::max(1, per_cu);
+  JERK_FFT_VARIANTS(X)
+#undef X
+  per_cu = std::max(per_cu, per_cu_k);
+  require(per_cu > 0, JERK_EINTERNAL, "unsupported FFT kernel variant");
+  return std::max(1, cus) * per_cu;
 }
 
-void fft_persistent_launch(const FftJob* d_jobs, BatchHeader* d_hdr, int32_t seg_len, const float2* twiddles,
-                           int32_t grid, hipStream_t stream) {
+void fft_persistent_launch(const FftJob* d_jobs, BatchHeader* d_hdr, int32_t seg_len, int32_t ept, bool keys,
+                           const float2* twiddles, int32_t grid, hipStream_t stream) {
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, d_hdr);
-  switch (seg_len) {
-    case 4096:
-      hipLaunchKernelGGL((fft_persistent_kernel<4096, 16, 16, 16, 16>), dim3(grid), dim3(256), 0, stream, d_jobs,
-                         d_hdr, twiddles);
-      break;
-    case 2048:
-      hipLaunchKernelGGL((fft_persistent_kernel<2048, 16, 8, 16, 16>), dim3(grid), dim3(128), 0, stream, d_jobs,
-                         d_hdr, twiddles);
-      break;
-    case 1024:
-      hipLaunchKernelGGL((fft_persistent_kernel<1024, 16, 4, 16, 16>), dim3(grid), dim3(64), 0, stream, d_jobs,
-                         d_hdr, twiddles);
-      break;
-    case 512:
-      hipLaunchKernelGGL((fft_persistent_kernel<512, 8, 8, 8, 8>), dim3(grid), dim3(64), 0, stream, d_jobs, d_hdr,
-                         twiddles);
-      break;
-    default:
-      throw Error(JERK_EINTERNAL, "unsupported segment length");
+#define X(S, E, A, B, C, D)                                                                                       \
+  if (seg_len == S && ept == E) {                                                                                 \
+    if (keys)                                                                                                     \
+      hipLaunchKernelGGL((fft_persistent_kernel<S, E, A, B, C, D, true>), dim3(grid), dim3(S / E), 0, stream,     \
+                         d_jobs, d_hdr, twiddles);                                                                \
+    else                                                                                                          \
+      hipLaunchKernelGGL((fft_persistent_kernel<S, E, A, B, C, D, false>), dim3(grid), dim3(S / E), 0, stream,    \
+                         d_jobs, d_hdr, twiddles);                                                                \
+    JERK_HIP_CHECK(hipGetLastError());                                                                            \
+    return;                                                                                                       \
   }
-  JERK_HIP_CHECK(hipGetLastError());
+  JERK_FFT_VARIANTS(X)
+#undef X
+  throw Error(JERK_EINTERNAL, "unsupported FFT kernel variant");
 }
 
 }  // namespace jerk

@@ -175,30 +175,39 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
         const bool imag = ks >= ksr;
         const int koff = (imag ? ks - ksr : ks) * 16 + khalf;
         const int p_re = imag ? 1 : 0;
+        // B fragments of every column tile first, then the products ordered so
+        // that consecutive MFMAs update different accumulators.
+        uint4 bhi[CT], blo[CT];
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
           const int x = c * 32 + col + koff;          // first element of this lane's 8
           const int w0 = (x - shift) >> 1;             // word index in copy `shift`
           const uint32_t* ph = lb + (p_re * 2 + shift) * WW + w0;
-          const uint4 bhi = make_uint4(ph[0], ph[1], ph[2], ph[3]);
+          bhi[c] = make_uint4(ph[0], ph[1], ph[2], ph[3]);
           if constexpr (SPLIT) {
             const uint32_t* pl = lb + ((p_re + 2) * 2 + shift) * WW + w0;
-            const uint4 blo = make_uint4(pl[0], pl[1], pl[2], pl[3]);
+            blo[c] = make_uint4(pl[0], pl[1], pl[2], pl[3]);
+          }
+        }
+        if constexpr (SPLIT) {
 #pragma unroll
-            for (int r = 0; r < RB; ++r) {
-              acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, afr[r][q][0]),
-                                                                 __builtin_bit_cast(bf16x8, bhi), acc[r][c], 0, 0, 0);
-              acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, afr[r][q][0]),
-                                                                 __builtin_bit_cast(bf16x8, blo), acc[r][c], 0, 0, 0);
-              acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, afr[r][q][1]),
-                                                                 __builtin_bit_cast(bf16x8, bhi), acc[r][c], 0, 0, 0);
-            }
-          } else {
+          for (int prod = 0; prod < 3; ++prod)
 #pragma unroll
             for (int r = 0; r < RB; ++r)
+#pragma unroll
+              for (int c = 0; c < CT; ++c) {
+                const uint4 av = prod == 2 ? afr[r][q][1] : afr[r][q][0];
+                const uint4 bv = prod == 1 ? blo[c] : bhi[c];
+                acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                                   __builtin_bit_cast(bf16x8, bv), acc[r][c], 0, 0, 0);
+              }
+        } else {
+#pragma unroll
+          for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
               acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, afr[r][q][0]),
-                                                                __builtin_bit_cast(f16x8, bhi), acc[r][c], 0, 0, 0);
-          }
+                                                                __builtin_bit_cast(f16x8, bhi[c]), acc[r][c], 0, 0, 0);
         }
       }
     }
@@ -212,8 +221,9 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
         if (m_local >= n_members) continue;
         const int t = a.members[a.m_begin + m_local];
         if (t < a.t_begin || t >= a.t_end) continue;
-        float2* __restrict__ row =
-            a.plane ? reinterpret_cast<float2*>(a.plane + (int64_t)(t - a.t_begin) * a.ld) + col0 : nullptr;
+        const int64_t orow = a.row_by_member ? (int64_t)(a.m_begin + m_local - a.row_base) : (int64_t)(t - a.t_begin);
+        if (orow < 0) continue;  // below the requested member range (same block of 8)
+        float2* __restrict__ row = a.plane ? reinterpret_cast<float2*>(a.plane + orow * a.ld) + col0 : nullptr;
         const int lim = (int)min((int64_t)COLS, a.nbins - col0);
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
@@ -252,8 +262,10 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
         const int m_local = (tblk * RB + r) * 8 + 2 * q + (lane >> 5);
         if ((lane & 31) == 0 && m_local < n_members) {
           const int t = a.members[a.m_begin + m_local];
-          if (t >= a.t_begin && t < a.t_end)
-            atomicMax(reinterpret_cast<unsigned long long*>(a.row_max + (t - a.t_begin)), (unsigned long long)k);
+          const int64_t orow =
+              a.row_by_member ? (int64_t)(a.m_begin + m_local - a.row_base) : (int64_t)(t - a.t_begin);
+          if (t >= a.t_begin && t < a.t_end && orow >= 0)
+            atomicMax(reinterpret_cast<unsigned long long*>(a.row_max + orow), (unsigned long long)k);
         }
       }
   }
@@ -355,9 +367,8 @@ void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream) {
   require(a.m_begin % 8 == 0, JERK_EINTERNAL, "GEMM member range must start on a block of 8");
   require(a.taps % 16 == 0 && a.taps >= 16 && a.taps <= 512, JERK_EINTERNAL, "GEMM taps out of range");
   const bool split = a.path != JERK_PATH_GEMM_FP16;
-  // Row blocks per wave: 2 while the group has enough templates and the tap
-  // fragments of 64 taps fit in registers, 1 otherwise.
-  const bool two = n_members > 8 && a.taps <= 64;
+  // One row block (8 templates) per wave; the tap fragments of up to 128 taps
+  // (split) or 256 taps (FP16) stay in registers across windows.
   // window = 64 outputs + taps + 8 slack elements, loaded 64 per lane-step
   if (a.row_max) {
     // peak-key launches keep one row block per wave (room for the per-row keys)
@@ -370,13 +381,11 @@ void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream) {
       else launch_cfg<1, 2, 16, 10, false, false, true>(a, stream);
     }
   } else if (split) {
-    if (two) launch_cfg<2, 2, 8, 3, true, true, false>(a, stream);
-    else if (a.taps <= 128) launch_cfg<1, 2, 16, 4, true, true, false>(a, stream);
+    if (a.taps <= 128) launch_cfg<1, 2, 16, 4, true, true, false>(a, stream);
     else if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false, false>(a, stream);
     else launch_cfg<1, 2, 8, 10, true, false, false>(a, stream);
   } else {
-    if (two) launch_cfg<2, 2, 8, 3, false, true, false>(a, stream);
-    else if (a.taps <= 256) launch_cfg<1, 2, 32, 6, false, true, false>(a, stream);
+    if (a.taps <= 256) launch_cfg<1, 2, 32, 6, false, true, false>(a, stream);
     else launch_cfg<1, 2, 16, 10, false, false, false>(a, stream);
   }
   JERK_HIP_CHECK(hipGetLastError());

@@ -38,6 +38,7 @@ inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a
 struct Group {
   int32_t taps = 0;        // K_g (multiple of the tap quantum)
   int32_t seg_len = 0;     // S_g
+  int32_t ept = 16;        // FFT kernel variant: complex elements per thread (8 or 16)
   int32_t tpb = 8;         // templates per workgroup (FFT path)
   int32_t path = JERK_PATH_FFT_FP32;
   std::vector<int32_t> members;  // template indices, ascending
@@ -96,7 +97,9 @@ struct FftJob {
   const float2* bank_fft;     // group's spectra, member 0 phase 0
   const int32_t* members;     // group's member list (device)
   int32_t m_begin, m_end;     // members to process
-  int32_t t_begin;            // output row of template t is t - t_begin
+  int32_t t_begin;            // output row of template t is t - t_begin ...
+  int32_t row_by_member;      // ... or, when set, mm - row_base for group member mm
+  int32_t row_base;
   int32_t taps, tpb;
   float* plane;               // plane rows (row stride ld floats), or null
   int64_t ld;
@@ -115,11 +118,14 @@ struct BatchHeader {
 // Sets j.n_seg and returns the job's tile count (segments x template blocks).
 int64_t fft_job_tiles(FftJob& j, int32_t seg_len);
 // twiddles: exp(-2 pi i k / seg_len), k < seg_len (complex64, device).
-void fft_correlate_launch(FftJob j, int32_t seg_len, const float2* twiddles, hipStream_t stream);
-void fft_persistent_launch(const FftJob* d_jobs, BatchHeader* d_hdr, int32_t seg_len, const float2* twiddles,
-                           int32_t grid, hipStream_t stream);
+// ept: complex elements per thread of the kernel variant (8 or 16).
+bool fft_variant_supported(int32_t seg_len, int32_t ept);
+void fft_correlate_launch(FftJob j, int32_t seg_len, int32_t ept, const float2* twiddles, hipStream_t stream);
+// keys: the jobs write peak keys (every job's row_max set) - selects the kernel instantiation.
+void fft_persistent_launch(const FftJob* d_jobs, BatchHeader* d_hdr, int32_t seg_len, int32_t ept, bool keys,
+                           const float2* twiddles, int32_t grid, hipStream_t stream);
 // Workgroups of the persistent kernel that fit on the current device at once.
-int32_t fft_persistent_grid(int32_t seg_len);
+int32_t fft_persistent_grid(int32_t seg_len, int32_t ept);
 
 // gemm_correlate.hip
 struct GemmArgs {
@@ -134,6 +140,8 @@ struct GemmArgs {
   int32_t taps;
   int32_t path;               // JERK_PATH_GEMM_SPLIT_BF16 or JERK_PATH_GEMM_FP16
   uint64_t* row_max;          // one peak key per row (atomicMax), or null; plane may then be null
+  int32_t row_by_member;      // output row is (member index - row_base) instead of t - t_begin
+  int32_t row_base;
 };
 void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream);
 size_t gemm_bank_bytes(int32_t n_members, int32_t taps, int32_t path);

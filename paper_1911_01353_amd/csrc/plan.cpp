@@ -63,6 +63,9 @@ int32_t default_seg_len(int32_t taps) {
   return 4096;
 }
 
+// Elements per thread of the default FFT kernel variant of a segment length.
+int32_t default_ept(int32_t seg_len) { return seg_len == 512 ? 8 : 16; }
+
 // Largest group width the split-BF16 path is chosen for under JERK_PATH_AUTO
 // (the FFT path's cost per output is nearly independent of the width, the
 // direct correlation's grows linearly with it).
@@ -163,6 +166,7 @@ void plan_build(Plan& p, const jerk_plan_desc& d) {
     require(g.taps <= 2048, JERK_EUNSUPPORTED, "template wider than 2048 taps");
     require(g.seg_len >= 2 * g.taps, JERK_EINVAL, "seg_len must be at least twice the widest group's taps");
     g.tpb = d.templates_per_block ? d.templates_per_block : 16;
+    g.ept = default_ept(g.seg_len);
     if (d.path == JERK_PATH_AUTO) {
       g.path = g.taps <= kAutoGemmMaxTaps ? JERK_PATH_GEMM_SPLIT_BF16 : JERK_PATH_FFT_FP32;
     } else {

@@ -146,7 +146,7 @@ struct jerk_server {
   bool stop = false;
   uint64_t next_ticket = 1, use_clock = 0;
   std::chrono::steady_clock::time_point t0;
-  int32_t grid_seg = 0, grid = 0;
+  int32_t grid_seg = 0, grid_ept = 0, grid = 0;
   int64_t fail_launch_at = 0, fail_build_at = 0, launch_count = 0, build_count = 0;
   bool paused = false;  // admission held (test hook)
   jerk_serve_stats st{};
@@ -346,7 +346,7 @@ bool dispatch(jerk_server& s, Slot& sl) {
       ready.push_back(q);
   if (ready.empty()) return false;
   const int64_t budget = s.d.tiles_per_launch;
-  std::vector<std::pair<FftJob, int32_t>> jobs;  // job, segment length
+  std::vector<std::pair<FftJob, std::pair<int32_t, int32_t>>> jobs;  // job, (segment length, elements/thread)
   std::vector<std::pair<Req*, Unit>> gemm;
   std::vector<std::pair<Req*, int>> taken;
   int64_t tiles = 0;
@@ -382,7 +382,7 @@ bool dispatch(jerk_server& s, Slot& sl) {
         j.ld = q->r.ld;
         j.row_max = reinterpret_cast<uint64_t*>(s.arena + q->mem_off);
         j.rmax_ld = 0;
-        jobs.push_back({j, g.seg_len});
+        jobs.push_back({j, {g.seg_len, g.ept}});
       } else {
         gemm.push_back({q, u});
       }
@@ -403,13 +403,14 @@ bool dispatch(jerk_server& s, Slot& sl) {
   for (auto& e : taken) JERK_HIP_CHECK(hipStreamWaitEvent(sl.stream, e.first->ready, 0));
   if (!jobs.empty()) {
     // one persistent launch per segment length present (normally one)
-    std::map<int32_t, std::vector<FftJob>> by_seg;
+    std::map<std::pair<int32_t, int32_t>, std::vector<FftJob>> by_seg;
     std::map<int32_t, const float2*> tw_of;
     for (auto& e : jobs) by_seg[e.second].push_back(e.first);
     for (auto& e : taken) {
       const Plan& p = e.first->bank->plan;
       for (auto& kv : by_seg)
-        tw_of[kv.first] = reinterpret_cast<const float2*>(s.arena + e.first->bank->off + p.off_tw[tw_slot(kv.first)]);
+        tw_of[kv.first.first] =
+            reinterpret_cast<const float2*>(s.arena + e.first->bank->off + p.off_tw[tw_slot(kv.first.first)]);
     }
     char* pinned = static_cast<char*>(sl.pinned);
     size_t poff = 0;
@@ -417,9 +418,10 @@ bool dispatch(jerk_server& s, Slot& sl) {
     for (auto& kv : by_seg) {
       std::vector<FftJob>& js = kv.second;
       int64_t total = 0;
+      const int32_t seg = kv.first.first, ept = kv.first.second;
       for (FftJob& j : js) {
         j.tile_begin = total;
-        total += fft_job_tiles(j, kv.first);
+        total += fft_job_tiles(j, seg);
       }
       BatchHeader h{};
       h.total_tiles = total;
@@ -429,12 +431,13 @@ bool dispatch(jerk_server& s, Slot& sl) {
       std::memcpy(pinned + poff, &h, sizeof(h));
       std::memcpy(pinned + poff + 256, js.data(), js.size() * sizeof(FftJob));
       JERK_HIP_CHECK(hipMemcpyAsync(dtab + poff, pinned + poff, bytes, hipMemcpyHostToDevice, sl.stream));
-      if (s.grid_seg != kv.first) {
-        s.grid = fft_persistent_grid(kv.first);
-        s.grid_seg = kv.first;
+      if (s.grid_seg != seg || s.grid_ept != ept) {
+        s.grid = fft_persistent_grid(seg, ept);
+        s.grid_seg = seg;
+        s.grid_ept = ept;
       }
       fft_persistent_launch(reinterpret_cast<const FftJob*>(dtab + poff + 256), reinterpret_cast<BatchHeader*>(dtab + poff),
-                            kv.first, tw_of[kv.first], (int32_t)std::min<int64_t>(s.grid, total), sl.stream);
+                            seg, ept, true, tw_of[seg], (int32_t)std::min<int64_t>(s.grid, total), sl.stream);
       poff += align_up(bytes);
     }
   }

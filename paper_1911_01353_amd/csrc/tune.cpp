@@ -24,7 +24,7 @@ constexpr int32_t kSegs[4] = {512, 1024, 2048, 4096};
 constexpr int32_t kTpbs[2] = {8, 16};
 
 struct Cand {
-  int32_t path, seg, tpb;
+  int32_t path, seg, tpb, ept;
 };
 // (device ordinal, taps, probe members, probe bins, allow MFMA) -> seconds per output point per candidate
 using Key = std::tuple<int, int32_t, int32_t, int64_t, bool>;
@@ -126,8 +126,10 @@ void autotune(Plan& p, const void* d_spec, int64_t nbins, void* d_scratch, size_
     std::vector<Cand> cands;
     for (int32_t seg : kSegs)
       if (seg >= 2 * g.taps)
-        for (int32_t tpb : kTpbs) cands.push_back({JERK_PATH_FFT_FP32, seg, tpb});
-    if (allow_gemm && g.taps <= 512) cands.push_back({JERK_PATH_GEMM_SPLIT_BF16, 0, 0});
+        for (int32_t ept : {8, 16})
+          if (fft_variant_supported(seg, ept))
+            for (int32_t tpb : kTpbs) cands.push_back({JERK_PATH_FFT_FP32, seg, tpb, ept});
+    if (allow_gemm && g.taps <= 512) cands.push_back({JERK_PATH_GEMM_SPLIT_BF16, 0, 0, 0});
     std::vector<std::pair<Cand, double>> res;
     for (const Cand& c : cands) {
       auto run = [&]() {
@@ -144,7 +146,7 @@ void autotune(Plan& p, const void* d_spec, int64_t nbins, void* d_scratch, size_
           j.tpb = c.tpb;
           j.plane = s.plane;
           j.ld = 2 * pb;
-          fft_correlate_launch(j, c.seg, s.tw[tw_slot(c.seg)], stream);
+          fft_correlate_launch(j, c.seg, c.ept, s.tw[tw_slot(c.seg)], stream);
         } else {
           GemmArgs a{};
           a.spec = static_cast<const float2*>(d_spec);
@@ -192,35 +194,42 @@ void autotune(Plan& p, const void* d_spec, int64_t nbins, void* d_scratch, size_
   JERK_HIP_CHECK(hipStreamSynchronize(stream));
   if (uniform) {
     // one segment length for all groups: least total estimated time
-    int32_t best_seg = 0;
+    int32_t best_seg = 0, best_ept = 0;
     double best_total = 0.0;
-    for (int32_t seg : kSegs) {
-      double total = 0.0;
-      bool ok = true;
-      for (size_t gi = 0; gi < p.groups.size() && ok; ++gi) {
-        double bt = -1.0;
-        for (auto& r : per_group[gi])
-          if (r.first.path == JERK_PATH_FFT_FP32 && r.first.seg == seg && (bt < 0 || r.second < bt)) bt = r.second;
-        if (bt < 0) ok = false;
-        else total += bt * (double)p.groups[gi].members.size();
+    for (int32_t seg : kSegs)
+      for (int32_t ept : {8, 16}) {
+        if (!fft_variant_supported(seg, ept)) continue;
+        double total = 0.0;
+        bool ok = true;
+        for (size_t gi = 0; gi < p.groups.size() && ok; ++gi) {
+          double bt = -1.0;
+          for (auto& r : per_group[gi])
+            if (r.first.path == JERK_PATH_FFT_FP32 && r.first.seg == seg && r.first.ept == ept &&
+                (bt < 0 || r.second < bt))
+              bt = r.second;
+          if (bt < 0) ok = false;
+          else total += bt * (double)p.groups[gi].members.size();
+        }
+        if (ok && (best_seg == 0 || total < best_total)) {
+          best_seg = seg;
+          best_ept = ept;
+          best_total = total;
+        }
       }
-      if (ok && (best_seg == 0 || total < best_total)) {
-        best_seg = seg;
-        best_total = total;
-      }
-    }
     require(best_seg != 0, JERK_EINTERNAL, "no common segment length");
     for (size_t gi = 0; gi < p.groups.size(); ++gi) {
-      Cand bc{JERK_PATH_FFT_FP32, best_seg, 16};
+      Cand bc{JERK_PATH_FFT_FP32, best_seg, 16, best_ept};
       double bt = -1.0;
       for (auto& r : per_group[gi])
-        if (r.first.path == JERK_PATH_FFT_FP32 && r.first.seg == best_seg && (bt < 0 || r.second < bt)) {
+        if (r.first.path == JERK_PATH_FFT_FP32 && r.first.seg == best_seg && r.first.ept == best_ept &&
+            (bt < 0 || r.second < bt)) {
           bt = r.second;
           bc = r.first;
         }
       p.groups[gi].path = JERK_PATH_FFT_FP32;
       p.groups[gi].seg_len = bc.seg;
       p.groups[gi].tpb = bc.tpb;
+      p.groups[gi].ept = bc.ept;
     }
   } else {
     for (size_t gi = 0; gi < p.groups.size(); ++gi) {
@@ -232,6 +241,7 @@ void autotune(Plan& p, const void* d_spec, int64_t nbins, void* d_scratch, size_
       if (best->first.path == JERK_PATH_FFT_FP32) {
         g.seg_len = best->first.seg;
         g.tpb = best->first.tpb;
+        g.ept = best->first.ept;
       }
     }
   }

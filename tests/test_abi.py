@@ -73,10 +73,10 @@ def test_groups_partition_templates_by_width():
 def test_bank_layout_grows_with_overrides():
     p = J.Plan(1 << 16, 20, 60, 2.0, 20.0, path="fft")
     b0 = p.info()["bank_bytes"]
-    p.set_group(0, 4096, 4, "fft")
+    p.set_group(0, 4096, 4, "fft", 8)
     assert p.info()["bank_bytes"] > b0
     g0 = p.group(0)
-    assert (g0["seg_len"], g0["templates_per_block"]) == (4096, 4)
+    assert (g0["seg_len"], g0["templates_per_block"], g0["fft_ept"]) == (4096, 4, 8)
 
 
 @pytest.mark.parametrize("kwargs,status", [

@@ -177,3 +177,27 @@ def test_2e22_bins_sampled_windows():
         torch.cuda.empty_cache()
         print(f"2^22 bins {path}: worst sampled error {worst:.3e}")
         assert worst <= 1e-4
+
+
+@pytest.mark.parametrize("path", ["fft", "split_bf16"])
+def test_member_slabs_match_full_plane(c1, path):
+    """jerk_search_members: rows indexed by group member equal the full plane's rows (bit-exact)."""
+    import torch
+    cfg, spec, grid, _ = c1
+    device()
+    plan = J.Plan(spec.shape[0], cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
+    bank = build_bank(plan)
+    full = gpu_plane(plan, bank, spec)
+    members = plan.members()
+    n = spec.shape[0]
+    d_spec = torch.from_numpy(spec).cuda()
+    for g, gi in enumerate(plan.groups()):
+        ms = members[gi["first_member"]: gi["first_member"] + gi["n_members"]]
+        for m0, m1 in [(0, gi["n_members"]), (3, min(gi["n_members"], 20)), (gi["n_members"] - 1, gi["n_members"])]:
+            if m1 <= m0:
+                continue
+            slab = torch.full((m1 - m0, 2 * n), float("nan"), dtype=torch.float32, device="cuda")
+            plan.search_members(bank, d_spec, slab, g, m0, m1)
+            torch.cuda.synchronize()
+            got = slab.cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), full[ms[m0:m1]].view(np.uint32)), (g, m0, m1)
