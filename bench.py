@@ -206,7 +206,7 @@ def plane_errors(J, torch):
     import numpy as np
     import synth
     from oracle import Grid, error_summary, oracle_plane, peak_index
-    cfg = synth.CONFIGS["c1"]
+    cfg = synth.CONFIGS["bins2e15_z20_w60"]
     spec_np = synth.make_spectrum(cfg)
     grid = Grid(cfg.zmax, cfg.wmax, cfg.dz, cfg.dw)
     ora = oracle_plane(spec_np, grid)
@@ -337,7 +337,7 @@ def main():
     J.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    cfg = synth.CONFIGS["c2"]
+    cfg = synth.CONFIGS["bins2e22_z200_w600"]
     spec_np = synth.make_spectrum(cfg)
     n = spec_np.shape[0]
     spec = torch.from_numpy(spec_np).cuda()

@@ -183,7 +183,13 @@ void plan_for(const jerk_server& s, const jerk_request& r, Plan& p) {
 size_t req_mem_bytes(int32_t T) { return align_up((size_t)T * 8) + align_up((size_t)T * sizeof(jerk_peak)); }
 
 void release_bank(jerk_server& s, BankEntry* b) {
-  if (b) b->refs--;
+  if (!b) return;
+  b->refs--;
+  if (b->failed && b->refs == 0) {  // a failed build is not kept: the next request rebuilds
+    if (!s.dry && b->ready) (void)hipEventDestroy(b->ready);
+    s.alloc.release(b->off, b->bytes);
+    s.banks.erase(b->key);
+  }
 }
 
 // Evicts least recently used banks nobody references until `need` bytes fit; true if they do.

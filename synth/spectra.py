@@ -13,8 +13,9 @@ accelerated/jerked tones stands in for them):
 4. Scale by ``1 / sqrt(mean_{k >= 1} |X_k|^2)`` (unit mean power).
 5. Round once to complex64.
 
-Config seeds: config ``k`` uses ``191100 + k``; spectrum ``i`` of a batch uses
-``seed * 1000 + i``.
+Seeds: the 2^15-bin single search uses 191101, the 2^22-bin search 191102, the
+256-spectrum batch 191103 and the request stream 191105; spectrum ``i`` of a
+batch uses ``seed * 1000 + i``.
 """
 
 from __future__ import annotations
@@ -119,10 +120,10 @@ def _config2_tones() -> tuple:
 
 CONFIGS = {
     # One spectrum, small grid: 2^16 samples, one tone at r0=8000.3, z0=6, w0=20.
-    "c1": SearchConfig("c1", 2 ** 16, 191101, 20.0, 60.0, 2.0, 20.0,
+    "bins2e15_z20_w60": SearchConfig("bins2e15_z20_w60", 2 ** 16, 191101, 20.0, 60.0, 2.0, 20.0,
                        (Tone(0.05, 8000.3, 6.0, 20.0, 0.0),)),
     # One realistic search: 2^23 samples, four seeded tones, 201 x 61 templates.
-    "c2": SearchConfig("c2", 2 ** 23, 191102, 200.0, 600.0, 2.0, 20.0, _config2_tones()),
+    "bins2e22_z200_w600": SearchConfig("bins2e22_z200_w600", 2 ** 23, 191102, 200.0, 600.0, 2.0, 20.0, _config2_tones()),
 }
 
 

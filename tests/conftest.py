@@ -14,6 +14,6 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session")
-def c1_spectrum():
+def small_spectrum():
     import synth
-    return synth.make_spectrum(synth.CONFIGS["c1"])
+    return synth.make_spectrum(synth.CONFIGS["bins2e15_z20_w60"])

@@ -23,7 +23,7 @@ TOL = {"fft": 1e-4, "split_bf16": 1e-4, "auto": 1e-4, "fp16": 1e-2}
 
 @pytest.fixture(scope="module")
 def c1():
-    cfg = synth.CONFIGS["c1"]
+    cfg = synth.CONFIGS["bins2e15_z20_w60"]
     spec = synth.make_spectrum(cfg)
     grid = Grid(cfg.zmax, cfg.wmax, cfg.dz, cfg.dw)
     ora = oracle_plane(spec, grid)
@@ -134,7 +134,7 @@ def test_2e22_bins_sampled_windows():
     """Full-size 2^22-bin search (201 x 61 templates): sampled rows and windows against the oracle."""
     import torch
     device()
-    cfg = synth.CONFIGS["c2"]
+    cfg = synth.CONFIGS["bins2e22_z200_w600"]
     spec = synth.make_spectrum(cfg)
     n = spec.shape[0]
     grid = Grid(cfg.zmax, cfg.wmax, cfg.dz, cfg.dw)

@@ -53,7 +53,7 @@ def test_half_width_against_sampled_sweep():
         assert half_width(zb, w, 0) == math.ceil(fmax)
 
 
-def test_grid_half_widths_config1():
+def test_grid_half_widths_small_search():
     g = Grid(20, 60, 2, 20)
     hs = g.half_widths()
     assert hs.min() == 16 and 2 * hs.max() == 62

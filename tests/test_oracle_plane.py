@@ -130,16 +130,16 @@ def test_correlate_row_edges_and_subrange():
     assert abs(full[k0] - acc) < 1e-12
 
 
-def test_config1_peak_at_injected_tone(c1_spectrum):
+def test_small_search_peak_at_injected_tone(small_spectrum):
     """The 2^15-bin config puts its peak where the tone's average (r, z, w) lies.
 
     Tone start values (r0, z0, w0) = (8000.3, 6, 20): rbar = 8006.633 (nearest
     half-bin r = 8006.5, p = 16013), zbar = 16 (i = 18), w = 20 (j = 4), so
     t = 4 * 21 + 18 = 102.
     """
-    cfg = synth.CONFIGS["c1"]
+    cfg = synth.CONFIGS["bins2e15_z20_w60"]
     g = Grid(cfg.zmax, cfg.wmax, cfg.dz, cfg.dw)
-    plane = oracle_plane(c1_spectrum, g, p_lo=15990, p_hi=16040)
+    plane = oracle_plane(small_spectrum, g, p_lo=15990, p_hi=16040)
     t, p = peak_index(plane)
     assert (t, 15990 + p) == (102, 16013)
     # a^2 N / 4 times captured energy, plus noise

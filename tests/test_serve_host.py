@@ -83,6 +83,10 @@ def test_injected_bank_build_failure():
     assert s.wait(bad, 10.0)["status"] == J.JERK_EHIP
     good = s.submit(FAKE_SPEC, 22, 66, nbins=1 << 16)
     assert s.wait(good, 10.0)["status"] == J.JERK_OK
+    # the failed bank is not cached: the same grid builds again and succeeds
+    again = s.submit(FAKE_SPEC, 20, 60, nbins=1 << 16)
+    assert s.wait(again, 10.0)["status"] == J.JERK_OK
+    assert s.stats()["bank_builds"] == 3
     s.close()
 
 
