@@ -52,6 +52,12 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load (arrival rate / service rate)")
     ap.add_argument("--batch-items", type=int, default=256,
                     help="spectra in the batched leg (uneven 2^20..2^22 bins); 0 skips it")
+    ap.add_argument("--rocfft-groups", type=int, default=4,
+                    help="width groups timed against an unfused rocFFT (torch.fft) overlap-save (0 = skip)")
+    ap.add_argument("--rocfft-members", type=int, default=16, help="templates per group in that comparison")
+    ap.add_argument("--cand-rows", type=int, default=512,
+                    help="plane rows of the 2^22-bin search timed through candidate selection (0 = skip)")
+    ap.add_argument("--cand-sigma", type=float, default=6.0, help="candidate threshold in row sigmas")
     ap.add_argument("--save-plan", default="", help="write the main plan's per-group configuration (JSON)")
     ap.add_argument("--load-plan", default="", help="use a saved per-group configuration instead of autotuning")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -166,7 +172,8 @@ def time_path(J, torch, spec, n, path, steps, warmup, slab_gb, want_kernels, aut
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     groups = plan.groups()
-    out = {"plan": plan, "wall": wall, "t_build": t_build, "t_tune": t_tune, "T": T, "rows": rows, "kernels": None,
+    del slab
+    out = {"plan": plan, "bank": bank, "wall": wall, "t_build": t_build, "t_tune": t_tune, "T": T, "rows": rows, "kernels": None,
            "groups": groups}
     if want_kernels:
         agg = {}
@@ -184,6 +191,138 @@ def time_path(J, torch, spec, n, path, steps, warmup, slab_gb, want_kernels, aut
             d["bytes"] += by
         out["kernels"] = agg
     return out
+
+
+def rocfft_overlap_save(torch, spec, spectra, taps, out):
+    """Unfused overlap-save with library FFTs: rows of `out` (float32 [m, 2n]) from template
+    spectra [m, 2, S] of K-tap templates.
+
+    Step by step, each step a separate library call that round-trips HBM: batched forward FFT of
+    all segments, pointwise product with every template spectrum, batched inverse FFT, power,
+    overlap strip and phase interleave. Template spectra are made beforehand (untimed), as a
+    library-based search would keep them.
+    """
+    n = spec.shape[0]
+    m, _, S = spectra.shape
+    K = taps
+    U = S - K + 1
+    n_seg = -(-n // U)
+    xp = torch.zeros(K // 2 - 1 + n_seg * U + S, dtype=torch.complex64, device=spec.device)
+    xp[K // 2 - 1: K // 2 - 1 + n] = spec
+    segs = xp.unfold(0, S, U)[:n_seg]
+    f = torch.fft.fft(segs)
+    for i in range(m):
+        y = torch.fft.ifft(f[None] * spectra[i][:, None, :])[..., :U]
+        pw = (y.real * y.real + y.imag * y.imag).reshape(2, n_seg * U)[:, :n]
+        out[i].view(n, 2).copy_(pw.t())
+
+
+def template_spectra(torch, taps, seg_len):
+    """H[f] = sum_j c_j e^{+2 pi i f j / S}: the spectrum that turns the circular product into the
+    correlation sum over taps."""
+    m, _, K = taps.shape
+    c = torch.zeros((m, 2, seg_len), dtype=torch.complex128, device=taps.device)
+    c[..., :K] = taps
+    return torch.fft.ifft(c, norm="forward").to(torch.complex64)
+
+
+def rocfft_leg(J, torch, plan, bank, spec, n, n_groups, members):
+    """The fused kernels against unfused rocFFT overlap-save on the same rows (best segment length
+    of the library path from 1024..8192), with the two planes compared."""
+    groups = plan.groups()
+    order = sorted(range(len(groups)), key=lambda g: groups[g]["taps"])
+    pick = sorted({order[int(round(i * (len(order) - 1) / max(1, n_groups - 1)))] for i in range(n_groups)})
+    res = []
+    for g in pick:
+        gi = groups[g]
+        m = min(members, gi["n_members"])
+        m0 = (gi["n_members"] - m) // 2
+        K = gi["taps"]
+        ours = torch.empty((m, 2 * n), dtype=torch.float32, device="cuda")
+        ref = torch.empty_like(ours)
+        plan.search_members(bank, spec, ours, g, m0, m0 + m)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        reps = 3
+        ev[0].record()
+        for _ in range(reps):
+            plan.search_members(bank, spec, ours, g, m0, m0 + m)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t_ours = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+        off = gi["taps_offset"] + (m0 * 2 * K) * 16
+        taps = bank[off: off + m * 2 * K * 16].view(torch.complex128).view(m, 2, K)
+        best = None
+        for S in (1024, 2048, 4096, 8192):
+            if S < 2 * K:
+                continue
+            spectra = template_spectra(torch, taps, S)
+            rocfft_overlap_save(torch, spec, spectra, K, ref)
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(reps):
+                rocfft_overlap_save(torch, spec, spectra, K, ref)
+            ev[1].record()
+            torch.cuda.synchronize()
+            t = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+            if best is None or t < best[1]:
+                best = (S, t)
+            del spectra
+        rowmean = ref.mean(dim=1, keepdim=True)
+        diff = ((ours - ref).abs() / torch.maximum(ref, rowmean)).max().item()
+        pts = m * 2 * n
+        res.append({"group": g, "taps": K, "path": ["fft_fp32", "split_bf16", "fp16"][gi["path"]],
+                    "members": m, "ours_points_per_s": pts / t_ours, "rocfft_points_per_s": pts / best[1],
+                    "rocfft_seg_len": best[0], "speedup": best[1] / t_ours, "max_rel_diff": diff})
+        print(f"[bench] rocFFT comparison group {g} K={K}: speedup {best[1] / t_ours:.2f} "
+              f"(diff {diff:.1e})", file=sys.stderr, flush=True)
+        del ours, ref
+    return res
+
+
+def candidates_leg(J, torch, plan, bank, spec, n, rows, k_sigma, reps=5):
+    """Row statistics and threshold peak-finding over a slab of real search rows (each kernel reads
+    the slab once: 4 B per point), timed with events on the current stream."""
+    groups = plan.groups()
+    members = plan.members()
+    slab = torch.empty((rows, 2 * n), dtype=torch.float32, device="cuda")
+    tmpl = []
+    r = 0
+    for g, gi in enumerate(groups):
+        if r >= rows:
+            break
+        m = min(gi["n_members"], rows - r)
+        plan.search_members(bank, spec, slab[r: r + m], g, 0, m)
+        tmpl += members[gi["first_member"]: gi["first_member"] + m].tolist()
+        r += m
+    rt = torch.tensor(tmpl, dtype=torch.int32, device="cuda")
+    stats = torch.empty((rows, 2), dtype=torch.float64, device="cuda")
+    ws = torch.empty(max(1, J.stats_workspace_bytes(rows, 2 * n)), dtype=torch.uint8, device="cuda")
+    cap = 1 << 22
+    out = torch.empty((cap, 4), dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_stats = t_cand = 0.0
+    for i in range(reps + 1):
+        count.zero_()
+        ev[0].record()
+        J.plane_stats(slab, stats, ws=ws)
+        ev[1].record()
+        J.find_candidates(slab, stats, k_sigma, out, count, row_template=rt)
+        ev[2].record()
+        torch.cuda.synchronize()
+        if i:
+            t_stats += ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+            t_cand += ev[1].elapsed_time(ev[2]) * 1e-3 / reps
+    pts = rows * 2 * n
+    found = int(count.item())
+    del slab, out
+    return {"rows": rows, "points": pts, "k_sigma": k_sigma, "candidates": found,
+            "stats_ms": t_stats * 1e3, "candidates_ms": t_cand * 1e3,
+            "points_per_s": pts / (t_stats + t_cand),
+            "stats_GBps": 4 * pts / t_stats / 1e9, "candidates_GBps": 4 * pts / t_cand / 1e9,
+            "stats_hbm_frac": 4 * pts / t_stats / 1e9 / HBM_PEAK_GBS,
+            "candidates_hbm_frac": 4 * pts / t_cand / 1e9 / HBM_PEAK_GBS}
 
 
 def cpu_baseline(spec, n_templates_sample):
@@ -396,6 +535,17 @@ def main():
             print(f"[bench] {p}: {paths[p]:.3e} points/s", file=sys.stderr, flush=True)
             r["plan"].close()
 
+    rocfft = None
+    if args.rocfft_groups > 0:
+        rocfft = rocfft_leg(J, torch, main_res["plan"], main_res["bank"], spec, n, args.rocfft_groups,
+                            args.rocfft_members)
+    cands = None
+    if args.cand_rows > 0:
+        cands = candidates_leg(J, torch, main_res["plan"], main_res["bank"], spec, n,
+                               min(args.cand_rows, T), args.cand_sigma)
+        print(f"[bench] candidate selection {cands['points_per_s']:.3e} points/s "
+              f"(stats {cands['stats_GBps']:.0f} GB/s, peaks {cands['candidates_GBps']:.0f} GB/s)",
+              file=sys.stderr, flush=True)
     errors = plane_errors(J, torch) if args.errors else None
     serving = None
     if args.serve_requests > 0:
@@ -429,6 +579,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "paths_points_per_s": paths,
+        "vs_unfused_rocfft": rocfft,
+        "candidate_selection": cands,
         "plane_error_2e15_bins": errors,
         "template_build_s": main_res["t_build"],
         "autotune_s": main_res["t_tune"],

@@ -220,6 +220,44 @@ typedef struct jerk_peak {
 int32_t jerk_peaks_reduce(const uint64_t* d_keys, int32_t rows, int64_t keys_per_row, int64_t keys_ld,
                           jerk_peak* d_out, hipStream_t stream);
 
+/* ---- candidate selection ------------------------------------------------------
+ * Paper, section "Results": the timed search includes the mean and standard deviation of
+ * the plane and a peak finder that keeps only peaks above a user threshold. Both work on
+ * plane slabs already in device memory: rows of n_r float powers with row stride ld. */
+
+/* A candidate: template t, plane index p (r = p / 2), its power and significance
+ * (power - mean) / sigma of its row. */
+typedef struct jerk_candidate {
+  uint32_t t;
+  uint32_t p;
+  float power;
+  float sigma;
+} jerk_candidate;
+
+/* Device workspace bytes jerk_plane_stats needs for `rows` rows of n_r points (0 if empty). */
+size_t jerk_stats_workspace_bytes(int32_t rows, int64_t n_r);
+/* Per-row population mean and standard deviation (divisor n_r) of a plane slab, accumulated in
+ * FP64, into d_stats[rows][2] = {mean, sigma} (device). One read of the slab; the result does
+ * not depend on scheduling, and a constant row gets sigma = 0 exactly. d_ws: caller device
+ * workspace of jerk_stats_workspace_bytes(rows, n_r) bytes. rows = 0 or n_r = 0 is a no-op.
+ * EINVAL for a NULL pointer or ld < n_r; ENOMEM for a short workspace. Asynchronous on stream. */
+int32_t jerk_plane_stats(const float* d_plane, int64_t ld, int32_t rows, int64_t n_r, double* d_stats,
+                         void* d_ws, size_t ws_bytes, hipStream_t stream);
+/* Appends the candidates of a plane slab to d_out: points whose power, widened to FP64, is
+ * strictly above mean + k_sigma * sigma of its row (d_stats as written by jerk_plane_stats)
+ * and that are peaks along r: strictly greater than the left neighbour and not less than the
+ * right one, the row's ends having no neighbour on that side. Row i is template
+ * d_row_template[i] (device int32 array) or, when that is NULL, t_base + i. *d_count (device)
+ * is incremented by the number of candidates found; a candidate whose slot index is
+ * >= capacity is counted but not stored, so several slabs can share one list and a count
+ * above capacity reports overflow. The caller clears *d_count before the first slab. The
+ * order of the list is unspecified. n_r must be < 2^32. EINVAL for a NULL pointer, ld < n_r
+ * or a non-finite k_sigma. Asynchronous on stream. */
+int32_t jerk_find_candidates(const float* d_plane, int64_t ld, int32_t rows, int64_t n_r, const double* d_stats,
+                             double k_sigma, const int32_t* d_row_template, int32_t t_base,
+                             jerk_candidate* d_out, int64_t capacity, unsigned long long* d_count,
+                             hipStream_t stream);
+
 /* ---- serving: continuous batching of search requests ----------------------- */
 typedef struct jerk_server jerk_server;
 

@@ -17,7 +17,8 @@ from ._lib import (JERK_EAGAIN, JERK_ECANCELED, JERK_EHIP, JERK_EINVAL, JERK_ENO
                    PATH_AUTO, PATH_FFT_FP32, PATH_GEMM_FP16, PATH_GEMM_SPLIT_BF16, PATH_NAMES, JerkError)
 
 __all__ = [
-    "Plan", "Server", "peaks_reduce", "JERK_EHIP", "JERK_ECANCELED", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
+    "Plan", "Server", "peaks_reduce", "stats_workspace_bytes", "plane_stats", "find_candidates",
+    "candidates_numpy", "CANDIDATE_DTYPE", "JERK_EHIP", "JERK_ECANCELED", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
     "PATH_AUTO", "PATH_NAMES", "JERK_OK", "JERK_EINVAL", "JERK_ENOMEM", "JERK_EAGAIN", "JERK_EPENDING",
 ]
 
@@ -218,6 +219,54 @@ def peaks_reduce(keys, keys_per_row: int, out, stream=None) -> None:
     rows = keys.shape[0]
     _lib.check(_lib.load().jerk_peaks_reduce(_dev_ptr(keys), rows, keys_per_row, keys.stride(0), _dev_ptr(out),
                                              _stream_ptr(stream)))
+
+
+CANDIDATE_DTYPE = np.dtype([("t", np.uint32), ("p", np.uint32), ("power", np.float32), ("sigma", np.float32)])
+
+
+def stats_workspace_bytes(rows: int, n_r: int) -> int:
+    return int(_lib.load().jerk_stats_workspace_bytes(rows, n_r))
+
+
+def plane_stats(plane, stats, n_r: int | None = None, ws=None, stream=None):
+    """Enqueue ``jerk_plane_stats`` on a (rows, >= n_r) float32 slab into stats (rows, 2) float64.
+
+    ``ws`` is a device uint8 tensor of at least ``stats_workspace_bytes`` bytes (allocated here
+    when omitted). Returns the workspace so that the caller can keep it alive with the stream.
+    """
+    import torch
+    rows = plane.shape[0]
+    n_r = plane.shape[1] if n_r is None else n_r
+    if plane.stride(1) != 1 or stats.shape[0] < rows or not stats.is_contiguous():
+        raise ValueError("plane rows must be contiguous and stats (rows, 2) contiguous")
+    need = stats_workspace_bytes(rows, n_r)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=plane.device)
+    _lib.check(_lib.load().jerk_plane_stats(_dev_ptr(plane), plane.stride(0), rows, n_r, _dev_ptr(stats),
+                                            _dev_ptr(ws), ws.numel(), _stream_ptr(stream)))
+    return ws
+
+
+def find_candidates(plane, stats, k_sigma: float, out, count, n_r: int | None = None, row_template=None,
+                    t_base: int = 0, stream=None) -> None:
+    """Enqueue ``jerk_find_candidates``: candidates of a (rows, >= n_r) slab appended to ``out``
+    (a (capacity, 4) int32 device tensor holding jerk_candidate records) and counted in ``count``
+    (a one-element int64 device tensor the caller zeroes first)."""
+    rows = plane.shape[0]
+    n_r = plane.shape[1] if n_r is None else n_r
+    if plane.stride(1) != 1 or out.dim() != 2 or out.shape[1] != 4 or not out.is_contiguous():
+        raise ValueError("plane rows must be contiguous and out a contiguous (capacity, 4) tensor")
+    rt = _dev_ptr(row_template) if row_template is not None else None
+    _lib.check(_lib.load().jerk_find_candidates(_dev_ptr(plane), plane.stride(0), rows, n_r, _dev_ptr(stats),
+                                                float(k_sigma), rt, t_base, _dev_ptr(out), out.shape[0],
+                                                _dev_ptr(count), _stream_ptr(stream)))
+
+
+def candidates_numpy(out, count) -> np.ndarray:
+    """Host copy of the stored candidates as a structured array sorted by (t, p)."""
+    n = min(int(count.item()), out.shape[0])
+    a = out[:n].cpu().numpy().view(CANDIDATE_DTYPE).reshape(n)
+    return np.sort(a, order=["t", "p"])
 
 
 class Server:

@@ -1,6 +1,8 @@
 // C ABI entry points: argument checks, status codes and per-thread error text.
 // No C++ exception crosses this boundary.
 #include <algorithm>
+#include <climits>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -345,6 +347,40 @@ int32_t jerk_peaks_reduce(const uint64_t* d_keys, int32_t rows, int64_t keys_per
     if (rows == 0) return;
     require(d_keys && d_out, JERK_EINVAL, "keys and output must not be NULL");
     jerk::peaks_reduce(d_keys, rows, keys_per_row, keys_ld, d_out, stream);
+  });
+}
+
+size_t jerk_stats_workspace_bytes(int32_t rows, int64_t n_r) {
+  if (rows < 0 || n_r < 0) return 0;
+  return jerk::stats_workspace_bytes(rows, n_r);
+}
+
+int32_t jerk_plane_stats(const float* d_plane, int64_t ld, int32_t rows, int64_t n_r, double* d_stats,
+                         void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    require(rows >= 0 && n_r >= 0 && ld >= n_r, JERK_EINVAL, "need rows >= 0, n_r >= 0 and ld >= n_r");
+    if (rows == 0 || n_r == 0) return;
+    require(d_plane && d_stats && d_ws, JERK_EINVAL, "plane, stats and workspace must not be NULL");
+    jerk::plane_stats(d_plane, ld, rows, n_r, d_stats, d_ws, ws_bytes, stream);
+  });
+}
+
+int32_t jerk_find_candidates(const float* d_plane, int64_t ld, int32_t rows, int64_t n_r, const double* d_stats,
+                             double k_sigma, const int32_t* d_row_template, int32_t t_base,
+                             jerk_candidate* d_out, int64_t capacity, unsigned long long* d_count,
+                             hipStream_t stream) {
+  return guarded([&] {
+    require(rows >= 0 && n_r >= 0 && ld >= n_r, JERK_EINVAL, "need rows >= 0, n_r >= 0 and ld >= n_r");
+    require(n_r < (int64_t(1) << 32), JERK_EINVAL, "n_r must be < 2^32");
+    require(std::isfinite(k_sigma), JERK_EINVAL, "k_sigma must be finite");
+    require(capacity >= 0, JERK_EINVAL, "capacity must be >= 0");
+    if (rows == 0 || n_r == 0) return;
+    require(d_plane && d_stats && d_count, JERK_EINVAL, "plane, stats and count must not be NULL");
+    require(d_out || capacity == 0, JERK_EINVAL, "output must not be NULL when capacity > 0");
+    require(d_row_template || (t_base >= 0 && (int64_t)t_base + rows - 1 <= INT32_MAX), JERK_EINVAL,
+            "t_base must be >= 0 and t_base + rows - 1 must fit int32");
+    jerk::find_candidates(d_plane, ld, rows, n_r, d_stats, k_sigma, d_row_template, t_base, d_out, capacity,
+                          d_count, stream);
   });
 }
 

@@ -166,6 +166,12 @@ void serve_inject(jerk_server& s, int32_t op, int64_t n);
 void serve_destroy(jerk_server* s);
 
 // reduce.hip
+size_t stats_workspace_bytes(int32_t rows, int64_t n_r);
+void plane_stats(const float* plane, int64_t ld, int32_t rows, int64_t n_r, double* stats, void* ws,
+                 size_t ws_bytes, hipStream_t stream);
+void find_candidates(const float* plane, int64_t ld, int32_t rows, int64_t n_r, const double* stats,
+                     double k_sigma, const int32_t* row_template, int32_t t_base, jerk_candidate* out,
+                     int64_t capacity, unsigned long long* count, hipStream_t stream);
 void peaks_reduce(const uint64_t* keys, int32_t rows, int64_t per_row, int64_t ld, jerk_peak* out,
                   hipStream_t stream);
 

@@ -137,3 +137,24 @@ def test_batch_argument_errors_without_gpu():
     assert lib.jerk_batch_search(fft.handle, fake, item, 1, 0, 147, fake, need, 0, null) == J.JERK_EINVAL
     # one key per FFT segment of the narrowest-output (widest) group
     assert fft.keys_per_row(4096) == -(-4096 // (1024 - 64 + 1))
+
+
+def test_candidate_entry_points_validate_on_the_host():
+    """Argument errors and empty slabs are decided before any device call."""
+    import ctypes as C
+    from paper_1911_01353_amd import _lib
+    lib = _lib.load()
+    one = C.c_void_p(1)
+    assert lib.jerk_stats_workspace_bytes(0, 100) == 0
+    assert lib.jerk_stats_workspace_bytes(3, 0) == 0
+    assert lib.jerk_stats_workspace_bytes(4, 1 << 23) >= 4 * 24
+    assert lib.jerk_plane_stats(None, 10, 0, 10, None, None, 0, None) == _lib.JERK_OK
+    assert lib.jerk_plane_stats(one, 5, 2, 10, one, one, 1 << 20, None) == _lib.JERK_EINVAL
+    assert lib.jerk_plane_stats(None, 10, 2, 10, one, one, 1 << 20, None) == _lib.JERK_EINVAL
+    f = lib.jerk_find_candidates
+    assert f(None, 10, 0, 10, None, 3.0, None, 0, None, 10, None, None) == _lib.JERK_OK
+    assert f(one, 10, 2, 10, one, float("nan"), None, 0, one, 10, one, None) == _lib.JERK_EINVAL
+    assert f(one, 10, 2, 10, one, 3.0, None, 0, None, 10, one, None) == _lib.JERK_EINVAL
+    assert f(one, 10, 2, 10, one, 3.0, None, -1, one, 10, one, None) == _lib.JERK_EINVAL
+    assert f(one, 1 << 32, 2, 1 << 32, one, 3.0, None, 0, one, 10, one, None) == _lib.JERK_EINVAL
+    assert f(one, 10, 2, 10, one, 3.0, None, 0, one, -1, one, None) == _lib.JERK_EINVAL

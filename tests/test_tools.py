@@ -56,3 +56,34 @@ def test_traffic_summary_scales_by_the_copy(tmp_path):
     assert abs(ent["fetch_bytes_per_point"] - 2000 * 1024 * 2 / 4096000) < 1e-9
     assert abs(ent["write_bytes_per_point"] - 8000 * 1024 / 4096000) < 1e-9
     assert ent["dispatches"] == 2
+
+
+def test_rocfft_comparator_matches_oracle():
+    """The unfused library overlap-save used as the bench's comparator computes the oracle's plane."""
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    import bench
+    from oracle.grid import Grid
+    from oracle.plane import oracle_plane
+    from oracle.response import template_taps
+    rng = np.random.default_rng(5)
+    n = 3001
+    x = ((rng.standard_normal(n) + 1j * rng.standard_normal(n)) / np.sqrt(2)).astype(np.complex64)
+    g = Grid(20.0, 60.0, 2.0, 20.0)
+    ts = [3, 77, 146]
+    K = max(2 * g.params(t)[2] for t in ts)
+    taps = np.zeros((len(ts), 2, K), dtype=np.complex128)
+    for i, t in enumerate(ts):
+        zb, w, h = g.params(t)
+        for ph in (0, 1):
+            # a narrower template sits centred in the group's K-tap window
+            off = K // 2 - h
+            taps[i, ph, off: off + 2 * h] = template_taps(zb, w, h, ph)
+    want = oracle_plane(x, g, templates=ts)
+    for S in (256, 512):
+        spectra = bench.template_spectra(torch, torch.from_numpy(taps), S)
+        out = torch.empty((len(ts), 2 * n), dtype=torch.float32)
+        bench.rocfft_overlap_save(torch, torch.from_numpy(x), spectra, K, out)
+        err = np.abs(out.numpy() - want) / np.maximum(want, want.mean(axis=1, keepdims=True))
+        assert err.max() < 1e-4
