@@ -220,6 +220,23 @@ typedef struct jerk_peak {
 int32_t jerk_peaks_reduce(const uint64_t* d_keys, int32_t rows, int64_t keys_per_row, int64_t keys_ld,
                           jerk_peak* d_out, hipStream_t stream);
 
+/* ---- spectrum preparation --------------------------------------------------------
+ * The search's input from a real time series (paper, section "Introduction": periodicity
+ * searches work on the Fourier transform of the series), in FP64 on the device: the DFT
+ * X[k] = sum_j x[j] exp(-2 pi i j k / N) of the N float32 samples, bins 0 .. N/2 - 1 kept
+ * (Nyquist dropped), X[0] set to 0, scaled by 1 / sqrt(mean over 1 <= k < N/2 of |X[k]|^2)
+ * (no scaling when that mean is 0), rounded once to complex64. */
+
+/* Device workspace bytes jerk_spectrum_prepare needs for n_samples samples (0 if invalid). */
+size_t jerk_spectrum_workspace_bytes(int64_t n_samples);
+/* d_series: n_samples float32 samples (device, 8-byte aligned); n_samples a power of two,
+ * 4 <= n_samples <= 2^30. d_spec: n_samples / 2 complex64 bins (device, interleaved re, im).
+ * d_ws: caller device workspace of jerk_spectrum_workspace_bytes(n_samples) bytes.
+ * EINVAL for a NULL or misaligned pointer, EUNSUPPORTED for a length that is not a power of
+ * two, ENOMEM for a short workspace. Asynchronous on stream. */
+int32_t jerk_spectrum_prepare(const float* d_series, int64_t n_samples, void* d_spec, void* d_ws,
+                              size_t ws_bytes, hipStream_t stream);
+
 /* ---- candidate selection ------------------------------------------------------
  * Paper, section "Results": the timed search includes the mean and standard deviation of
  * the plane and a peak finder that keeps only peaks above a user threshold. Both work on

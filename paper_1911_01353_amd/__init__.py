@@ -18,7 +18,7 @@ from ._lib import (JERK_EAGAIN, JERK_ECANCELED, JERK_EHIP, JERK_EINVAL, JERK_ENO
 
 __all__ = [
     "Plan", "Server", "peaks_reduce", "stats_workspace_bytes", "plane_stats", "find_candidates",
-    "candidates_numpy", "CANDIDATE_DTYPE", "JERK_EHIP", "JERK_ECANCELED", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
+    "candidates_numpy", "CANDIDATE_DTYPE", "spectrum_workspace_bytes", "prepare_spectrum", "JERK_EHIP", "JERK_ECANCELED", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
     "PATH_AUTO", "PATH_NAMES", "JERK_OK", "JERK_EINVAL", "JERK_ENOMEM", "JERK_EAGAIN", "JERK_EPENDING",
 ]
 
@@ -219,6 +219,29 @@ def peaks_reduce(keys, keys_per_row: int, out, stream=None) -> None:
     rows = keys.shape[0]
     _lib.check(_lib.load().jerk_peaks_reduce(_dev_ptr(keys), rows, keys_per_row, keys.stride(0), _dev_ptr(out),
                                              _stream_ptr(stream)))
+
+
+def spectrum_workspace_bytes(n_samples: int) -> int:
+    return int(_lib.load().jerk_spectrum_workspace_bytes(n_samples))
+
+
+def prepare_spectrum(series, out=None, ws=None, stream=None):
+    """Enqueue ``jerk_spectrum_prepare``: float32 device series of N samples -> complex64 device
+    spectrum of N/2 bins (``out``, allocated here when omitted). Returns ``(out, ws)``; keep the
+    workspace alive until the stream has run."""
+    import torch
+    n = series.shape[0]
+    if series.dtype != torch.float32 or not series.is_contiguous():
+        raise ValueError("series must be a contiguous float32 tensor")
+    if out is None:
+        out = torch.empty(n // 2, dtype=torch.complex64, device=series.device)
+    if out.dtype != torch.complex64 or out.numel() < n // 2 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous complex64 tensor of n/2 bins")
+    if ws is None:
+        ws = torch.empty(max(spectrum_workspace_bytes(n), 1), dtype=torch.uint8, device=series.device)
+    _lib.check(_lib.load().jerk_spectrum_prepare(_dev_ptr(series), n, _dev_ptr(out), _dev_ptr(ws), ws.numel(),
+                                                 _stream_ptr(stream)))
+    return out, ws
 
 
 CANDIDATE_DTYPE = np.dtype([("t", np.uint32), ("p", np.uint32), ("power", np.float32), ("sigma", np.float32)])

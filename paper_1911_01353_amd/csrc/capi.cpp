@@ -350,6 +350,26 @@ int32_t jerk_peaks_reduce(const uint64_t* d_keys, int32_t rows, int64_t keys_per
   });
 }
 
+static bool spectrum_length_ok(int64_t n) { return n >= 4 && n <= (int64_t(1) << 30) && (n & (n - 1)) == 0; }
+
+size_t jerk_spectrum_workspace_bytes(int64_t n_samples) {
+  if (!spectrum_length_ok(n_samples)) return 0;
+  return jerk::spectrum_workspace_bytes(n_samples);
+}
+
+int32_t jerk_spectrum_prepare(const float* d_series, int64_t n_samples, void* d_spec, void* d_ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    require(n_samples >= 4 && n_samples <= (int64_t(1) << 30), JERK_EINVAL, "n_samples must be in [4, 2^30]");
+    require(spectrum_length_ok(n_samples), JERK_EUNSUPPORTED, "n_samples must be a power of two");
+    require(d_series && d_spec && d_ws, JERK_EINVAL, "series, spectrum and workspace must not be NULL");
+    require((reinterpret_cast<uintptr_t>(d_series) & 7u) == 0 && (reinterpret_cast<uintptr_t>(d_spec) & 7u) == 0 &&
+                (reinterpret_cast<uintptr_t>(d_ws) & 15u) == 0,
+            JERK_EINVAL, "series and spectrum must be 8-byte aligned, the workspace 16-byte aligned");
+    jerk::spectrum_prepare(d_series, n_samples, static_cast<float2*>(d_spec), d_ws, ws_bytes, stream);
+  });
+}
+
 size_t jerk_stats_workspace_bytes(int32_t rows, int64_t n_r) {
   if (rows < 0 || n_r < 0) return 0;
   return jerk::stats_workspace_bytes(rows, n_r);

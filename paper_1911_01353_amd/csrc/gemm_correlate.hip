@@ -8,9 +8,9 @@
 // with b_j = conj(T(h - 1 - j + phase/2)) the template's taps. The spectrum
 // operand is a Hankel matrix B[kk][n] = X[base + n + kk]; it is never formed:
 // a window of the spectrum sits in LDS and each lane reads 8 consecutive
-// values of it. Eight copies of the window, shifted by 0..7 elements, make
-// every such read a 16-byte-aligned ds_read_b128 (the shift a lane needs is
-// fixed by its column).
+// values of it. Two copies of the window, the second shifted by one element,
+// make every such read four aligned 32-bit words (which copy a lane reads is
+// fixed by the parity of its column).
 //
 // Split-BF16: X = X_hi + X_lo and A = A_hi + A_lo with bf16 parts; the
 // product keeps A_hi X_hi + A_hi X_lo + A_lo X_hi (FP32 accumulation), a

@@ -166,6 +166,9 @@ void serve_inject(jerk_server& s, int32_t op, int64_t n);
 void serve_destroy(jerk_server* s);
 
 // reduce.hip
+size_t spectrum_workspace_bytes(int64_t n_samples);
+void spectrum_prepare(const float* series, int64_t n_samples, float2* spec, void* ws, size_t ws_bytes,
+                      hipStream_t stream);
 size_t stats_workspace_bytes(int32_t rows, int64_t n_r);
 void plane_stats(const float* plane, int64_t ld, int32_t rows, int64_t n_r, double* stats, void* ws,
                  size_t ws_bytes, hipStream_t stream);

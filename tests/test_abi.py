@@ -158,3 +158,18 @@ def test_candidate_entry_points_validate_on_the_host():
     assert f(one, 10, 2, 10, one, 3.0, None, -1, one, 10, one, None) == _lib.JERK_EINVAL
     assert f(one, 1 << 32, 2, 1 << 32, one, 3.0, None, 0, one, 10, one, None) == _lib.JERK_EINVAL
     assert f(one, 10, 2, 10, one, 3.0, None, 0, one, -1, one, None) == _lib.JERK_EINVAL
+
+
+def test_spectrum_entry_point_validates_on_the_host():
+    import ctypes as C
+    from paper_1911_01353_amd import _lib
+    lib = _lib.load()
+    one = C.c_void_p(256)
+    assert lib.jerk_spectrum_workspace_bytes(1 << 23) >= (1 << 22) * 32
+    for bad in (0, 2, 3, 6, 1000):
+        assert lib.jerk_spectrum_workspace_bytes(bad) == 0
+    assert lib.jerk_spectrum_prepare(one, 1000, one, one, 1 << 30, None) == _lib.JERK_EUNSUPPORTED
+    assert lib.jerk_spectrum_prepare(one, 2, one, one, 1 << 30, None) == _lib.JERK_EINVAL
+    assert lib.jerk_spectrum_prepare(None, 1024, one, one, 1 << 30, None) == _lib.JERK_EINVAL
+    assert lib.jerk_spectrum_prepare(C.c_void_p(260), 1024, one, one, 1 << 30, None) == _lib.JERK_EINVAL
+    assert lib.jerk_spectrum_prepare(one, 1024, one, one, 16, None) == _lib.JERK_ENOMEM
