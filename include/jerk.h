@@ -220,6 +220,26 @@ typedef struct jerk_peak {
 int32_t jerk_peaks_reduce(const uint64_t* d_keys, int32_t rows, int64_t keys_per_row, int64_t keys_ld,
                           jerk_peak* d_out, hipStream_t stream);
 
+/* ---- harmonic summing ------------------------------------------------------------
+ * The stage after matched filtering (paper, section "Results": the harmonic sum improves
+ * the sensitivity of Fourier searches and costs at least as much as the filtering; the
+ * paper gives no definition). The h-th harmonic of a signal with fundamental (r, zbar, w)
+ * lies at (h r, h zbar, h w); with zmax a multiple of dz every harmonic of a lattice point
+ * is a lattice point, and S_H(r, zbar, w) = sum_{h=1}^{H} P(h r, h zbar, h w) (FP32 sum,
+ * h ascending). Fundamentals are kept when all H harmonics lie on the plane:
+ * |zbar| <= floor(zmax / dz / H) dz, |w| <= floor(J / H) dw and H p <= n_r - 1. */
+
+/* Shape of S_H for a plane of n_r points per row: n_zf x n_wf fundamental templates (rows
+ * ordered like the plan's lattice, w-major, zbar and w centred on 0) of n_pf points each.
+ * EUNSUPPORTED when zmax is not a multiple of dz; EINVAL unless 1 <= n_harm <= 64, n_r >= 1. */
+int32_t jerk_harmonic_shape(const jerk_plan* plan, int64_t n_r, int32_t n_harm, int32_t* n_zf, int32_t* n_wf,
+                            int64_t* n_pf);
+/* S_H of a full plane d_plane (device; every template of the plan, row t at t * ld, n_r
+ * points per row, e.g. jerk_search over [0, T)) into d_out (device; row f at f * out_ld,
+ * n_pf points). EINVAL for NULL pointers, ld < n_r or out_ld < n_pf. Asynchronous on stream. */
+int32_t jerk_harmonic_sum(const jerk_plan* plan, const float* d_plane, int64_t ld, int64_t n_r, int32_t n_harm,
+                          float* d_out, int64_t out_ld, hipStream_t stream);
+
 /* ---- spectrum preparation --------------------------------------------------------
  * The search's input from a real time series (paper, section "Introduction": periodicity
  * searches work on the Fourier transform of the series), in FP64 on the device: the DFT

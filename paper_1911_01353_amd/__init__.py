@@ -195,6 +195,28 @@ class Plan:
                                                  _dev_ptr(ws), ws.numel() * ws.element_size(),
                                                  _lib.BATCH_GRAPH if graph else 0, _stream_ptr(stream)))
 
+    def harmonic_shape(self, n_r: int, n_harm: int) -> tuple:
+        """(n_zf, n_wf, n_pf) of the harmonic sum of n_harm harmonics (``jerk_harmonic_shape``)."""
+        zf, wf, pf = C.c_int32(), C.c_int32(), C.c_int64()
+        _lib.check(_lib.load().jerk_harmonic_shape(self.handle, n_r, n_harm, C.byref(zf), C.byref(wf), C.byref(pf)))
+        return zf.value, wf.value, pf.value
+
+    def harmonic_sum(self, plane, n_harm: int, out=None, n_r: int | None = None, stream=None):
+        """Enqueue ``jerk_harmonic_sum`` over a full (T, >= n_r) float32 plane; returns ``out``
+        ((n_zf * n_wf, >= n_pf) float32, allocated here when omitted)."""
+        import torch
+        n_r = plane.shape[1] if n_r is None else n_r
+        zf, wf, pf = self.harmonic_shape(n_r, n_harm)
+        if plane.shape[0] != self.info()["n_templates"] or plane.stride(1) != 1:
+            raise ValueError("plane must hold every template, rows contiguous")
+        if out is None:
+            out = torch.empty((zf * wf, pf), dtype=torch.float32, device=plane.device)
+        if out.shape[0] < zf * wf or out.shape[1] < pf or out.stride(1) != 1:
+            raise ValueError("out too small")
+        _lib.check(_lib.load().jerk_harmonic_sum(self.handle, _dev_ptr(plane), plane.stride(0), n_r, n_harm,
+                                                 _dev_ptr(out), out.stride(0), _stream_ptr(stream)))
+        return out
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
             _lib.load().jerk_plan_destroy(self._h)

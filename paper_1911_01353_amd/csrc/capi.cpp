@@ -350,6 +350,25 @@ int32_t jerk_peaks_reduce(const uint64_t* d_keys, int32_t rows, int64_t keys_per
   });
 }
 
+int32_t jerk_harmonic_shape(const jerk_plan* plan, int64_t n_r, int32_t n_harm, int32_t* n_zf, int32_t* n_wf,
+                            int64_t* n_pf) {
+  return guarded([&] {
+    require(plan && n_zf && n_wf && n_pf, JERK_EINVAL, "plan and outputs must not be NULL");
+    const jerk::HarmonicShape s = jerk::harmonic_shape(plan->p, n_r, n_harm);
+    *n_zf = s.n_zf;
+    *n_wf = s.n_wf;
+    *n_pf = s.n_pf;
+  });
+}
+
+int32_t jerk_harmonic_sum(const jerk_plan* plan, const float* d_plane, int64_t ld, int64_t n_r, int32_t n_harm,
+                          float* d_out, int64_t out_ld, hipStream_t stream) {
+  return guarded([&] {
+    require(plan && d_plane && d_out, JERK_EINVAL, "plan, plane and output must not be NULL");
+    jerk::harmonic_sum(plan->p, d_plane, ld, n_r, n_harm, d_out, out_ld, stream);
+  });
+}
+
 static bool spectrum_length_ok(int64_t n) { return n >= 4 && n <= (int64_t(1) << 30) && (n & (n - 1)) == 0; }
 
 size_t jerk_spectrum_workspace_bytes(int64_t n_samples) {

@@ -166,6 +166,14 @@ void serve_inject(jerk_server& s, int32_t op, int64_t n);
 void serve_destroy(jerk_server* s);
 
 // reduce.hip
+// harmonics.hip
+struct HarmonicShape {
+  int32_t i0 = 0, n_zf = 0, n_wf = 0;
+  int64_t n_pf = 0;
+};
+HarmonicShape harmonic_shape(const Plan& p, int64_t n_r, int32_t n_harm);
+void harmonic_sum(const Plan& p, const float* plane, int64_t ld, int64_t n_r, int32_t n_harm, float* out,
+                  int64_t out_ld, hipStream_t stream);
 size_t spectrum_workspace_bytes(int64_t n_samples);
 void spectrum_prepare(const float* series, int64_t n_samples, float2* spec, void* ws, size_t ws_bytes,
                       hipStream_t stream);

@@ -173,3 +173,28 @@ def test_spectrum_entry_point_validates_on_the_host():
     assert lib.jerk_spectrum_prepare(None, 1024, one, one, 1 << 30, None) == _lib.JERK_EINVAL
     assert lib.jerk_spectrum_prepare(C.c_void_p(260), 1024, one, one, 1 << 30, None) == _lib.JERK_EINVAL
     assert lib.jerk_spectrum_prepare(one, 1024, one, one, 16, None) == _lib.JERK_ENOMEM
+
+
+def test_harmonic_shape_matches_the_oracle_and_validates():
+    import ctypes as C
+    from paper_1911_01353_amd import _lib
+    from oracle import Grid
+    from oracle.harmonics import fundamental_shape
+    for zmax, wmax, n_r, H in [(200.0, 600.0, 1 << 23, 2), (200.0, 600.0, 1 << 23, 3), (20.0, 60.0, 65536, 4),
+                               (24.0, 80.0, 8192, 4), (50.0, 150.0, 1000, 1), (6.0, 0.0, 17, 8)]:
+        plan = J.Plan(1024, zmax, wmax, 2.0, 20.0, path="fft")
+        assert plan.harmonic_shape(n_r, H) == fundamental_shape(Grid(zmax, wmax, 2.0, 20.0), n_r, H)
+        plan.close()
+    plan = J.Plan(1024, 21.0, 60.0, 2.0, 20.0, path="fft")
+    lib = _lib.load()
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int64()
+    assert lib.jerk_harmonic_shape(plan.handle, 100, 2, C.byref(a), C.byref(b), C.byref(c)) == _lib.JERK_EUNSUPPORTED
+    plan.close()
+    plan = J.Plan(1024, 20.0, 60.0, 2.0, 20.0, path="fft")
+    assert lib.jerk_harmonic_shape(plan.handle, 100, 0, C.byref(a), C.byref(b), C.byref(c)) == _lib.JERK_EINVAL
+    assert lib.jerk_harmonic_shape(plan.handle, 100, 65, C.byref(a), C.byref(b), C.byref(c)) == _lib.JERK_EINVAL
+    one = C.c_void_p(256)
+    assert lib.jerk_harmonic_sum(plan.handle, None, 100, 100, 2, one, 100, None) == _lib.JERK_EINVAL
+    assert lib.jerk_harmonic_sum(plan.handle, one, 99, 100, 2, one, 100, None) == _lib.JERK_EINVAL
+    assert lib.jerk_harmonic_sum(plan.handle, one, 100, 100, 2, one, 49, None) == _lib.JERK_EINVAL
+    plan.close()

@@ -1,0 +1,91 @@
+"""GPU harmonic summing against the oracle.
+
+Integer-valued planes built from lattice coordinates are summed exactly in FP32,
+so those results must be bit-equal to the oracle's closed forms. On real planes
+the GPU sums H FP32 values in order and the oracle in FP64: relative error at
+most H * 2^-24 per point (all terms are non-negative).
+"""
+
+import numpy as np
+import pytest
+
+import paper_1911_01353_amd as J
+import synth
+from oracle import Grid
+from oracle.harmonics import fundamental_params, harmonic_sum
+
+from gpu_helpers import build_bank, device
+
+pytestmark = pytest.mark.gpu
+
+
+def _upload(a, ld=None, pad=7.0):
+    import torch
+    dev = device()
+    rows, n = a.shape
+    ld = ld or n
+    t = torch.full((rows, ld), pad, dtype=torch.float32, device=dev)
+    t[:, :n] = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    return t
+
+
+@pytest.mark.parametrize("H", [1, 2, 3, 4, 8])
+def test_coordinate_planes_exact(H):
+    import torch
+    zmax, wmax = 16.0, 80.0
+    g = Grid(zmax, wmax, 2.0, 20.0)
+    plan = J.Plan(512, zmax, wmax, 2.0, 20.0, path="fft")
+    n_r = 1031
+    p = np.arange(n_r)
+    for f in (lambda z, w: p, lambda z, w: z + 1000.0 + 0 * p, lambda z, w: w + 5000.0 + 0 * p):
+        plane = np.stack([f(g.zbar(t), g.w(t)) for t in range(g.n_templates)]).astype(np.float64)
+        dev_plane = _upload(plane, ld=n_r + 5)
+        zf, wf, pf = plan.harmonic_shape(n_r, H)
+        out = torch.full((zf * wf, pf + 3), -1.0, dtype=torch.float32, device=device())
+        plan.harmonic_sum(dev_plane, H, out=out, n_r=n_r)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert np.array_equal(got[:, :pf], harmonic_sum(plane, g, H).astype(np.float32))
+        assert np.all(got[:, pf:] == -1.0)
+    plan.close()
+
+
+def test_search_plane_2e15_bins(small_spectrum):
+    import torch
+    cfg = synth.CONFIGS["bins2e15_z20_w60"]
+    n = small_spectrum.shape[0]
+    g = Grid(cfg.zmax, cfg.wmax, cfg.dz, cfg.dw)
+    plan = J.Plan(n, cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path="fft")
+    bank = build_bank(plan)
+    T = plan.info()["n_templates"]
+    plane = torch.empty((T, 2 * n), dtype=torch.float32, device=device())
+    plan.search(bank, torch.from_numpy(small_spectrum).to(device()), plane, 0, T)
+    host = plane.cpu().numpy()
+    for H in (2, 3, 4):
+        got = plan.harmonic_sum(plane, H).cpu().numpy()
+        want = harmonic_sum(host, g, H)
+        assert got.shape == want.shape
+        assert np.max(np.abs(got - want) / np.maximum(want, 1e-30)) <= H * 2.0 ** -24 * 1.01
+
+
+def test_periodic_signal_end_to_end():
+    """Series -> spectrum -> plane -> harmonic sum on the device peaks at the fundamental."""
+    import torch
+    n_t = 1 << 13
+    rbar, zb, w = 400.0, 6.0, 20.0
+    z0 = zb - w / 2
+    r0 = rbar - z0 / 2 - w / 6
+    tones = tuple(synth.Tone(0.15, h * r0, h * z0, h * w, 0.3 * h) for h in range(1, 5))
+    x = torch.from_numpy(synth.time_series(n_t, 5, tones)).to(device())
+    spec, _ws = J.prepare_spectrum(x)
+    n = n_t // 2
+    plan = J.Plan(n, 24.0, 80.0, 2.0, 20.0, path="fft")
+    bank = build_bank(plan)
+    T = plan.info()["n_templates"]
+    plane = torch.empty((T, 2 * n), dtype=torch.float32, device=device())
+    plan.search(bank, spec, plane, 0, T)
+    s = plan.harmonic_sum(plane, 4)
+    torch.cuda.synchronize()
+    row, p = divmod(int(torch.argmax(s).item()), s.shape[1])
+    assert fundamental_params(Grid(24.0, 80.0, 2.0, 20.0), 4, row) == (zb, w)
+    assert p == int(2 * rbar)
