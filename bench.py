@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--cand-rows", type=int, default=512,
                     help="plane rows of the 2^22-bin search timed through candidate selection (0 = skip)")
     ap.add_argument("--cand-sigma", type=float, default=6.0, help="candidate threshold in row sigmas")
+    ap.add_argument("--harm-templates", type=int, default=1,
+                    help="time harmonic sums (H = 2, 4, 8) over a 147-template plane of the 2^22-bin spectrum")
     ap.add_argument("--save-plan", default="", help="write the main plan's per-group configuration (JSON)")
     ap.add_argument("--load-plan", default="", help="use a saved per-group configuration instead of autotuning")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -325,6 +327,35 @@ def candidates_leg(J, torch, plan, bank, spec, n, rows, k_sigma, reps=5):
             "candidates_hbm_frac": 4 * pts / t_cand / 1e9 / HBM_PEAK_GBS}
 
 
+def harmonics_leg(J, torch, spec, n, reps=5):
+    """Harmonic sums of the full plane of a 147-template grid (zmax 20, wmax 60) of the 2^22-bin
+    spectrum (4.9 GB), for H = 2, 4, 8; algorithmic bytes 4 (H + 1) per output point."""
+    plan = J.Plan(n, 20.0, 60.0, 2.0, 20.0, path="fft")
+    bank = plan.new_bank()
+    plan.build_templates(bank)
+    T = plan.info()["n_templates"]
+    plane = torch.empty((T, 2 * n), dtype=torch.float32, device="cuda")
+    plan.search(bank, spec, plane, 0, T)
+    res = {"workload": f"full plane of {T} templates (zmax 20, wmax 60) x {2 * n} points"}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for H in (2, 4, 8):
+        out = plan.harmonic_sum(plane, H)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            plan.harmonic_sum(plane, H, out=out)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+        pts = out.numel()
+        res[f"H{H}"] = {"output_points": pts, "ms": t * 1e3, "points_per_s": pts / t,
+                        "GBps": 4 * (H + 1) * pts / t / 1e9, "hbm_frac": 4 * (H + 1) * pts / t / 1e9 / HBM_PEAK_GBS}
+        del out
+    del plane, bank
+    plan.close()
+    return res
+
+
 def cpu_baseline(spec, n_templates_sample):
     """The FP64 oracle, single-threaded, on full rows of a sample of templates."""
     import numpy as np
@@ -546,6 +577,10 @@ def main():
         print(f"[bench] candidate selection {cands['points_per_s']:.3e} points/s "
               f"(stats {cands['stats_GBps']:.0f} GB/s, peaks {cands['candidates_GBps']:.0f} GB/s)",
               file=sys.stderr, flush=True)
+    harm = harmonics_leg(J, torch, spec, n) if args.harm_templates else None
+    if harm:
+        print(f"[bench] harmonic sums: " + ", ".join(f"H={h[1:]} {v['GBps']:.0f} GB/s" for h, v in harm.items()
+                                                       if h.startswith("H")), file=sys.stderr, flush=True)
     errors = plane_errors(J, torch) if args.errors else None
     serving = None
     if args.serve_requests > 0:
@@ -581,6 +616,7 @@ def main():
         "paths_points_per_s": paths,
         "vs_unfused_rocfft": rocfft,
         "candidate_selection": cands,
+        "harmonic_sums": harm,
         "plane_error_2e15_bins": errors,
         "template_build_s": main_res["t_build"],
         "autotune_s": main_res["t_tune"],
