@@ -8,7 +8,10 @@
 // sub-transform length L and radix R reads in[b + r M/R], r < R, multiplies by
 // the twiddle w_{LR}^{r j} (j = b mod L) and writes the R-point DFT to
 // out[j + L (r' + R q)], b = j + L q: after the last pass the result is in
-// natural order. Twiddles and DFT constants come from sincospi in FP64.
+// natural order. Twiddles come from sincospi in FP64; the R-point DFTs are
+// radix-2 butterflies, so a constant input gives exact zeros above DC (as a
+// butterfly FFT in FP64 on the host does) rather than rounding noise that the
+// normalisation would then blow up.
 //
 // The real spectrum follows from E[k] = (Z[k] + conj Z[M-k]) / 2 (even samples),
 // O[k] = (Z[k] - conj Z[M-k]) / (2i) (odd samples) and X[k] = E[k] + e^{-2 pi i k / N} O[k],
@@ -30,6 +33,31 @@ __device__ __forceinline__ double2 unit(double turns_times_two) {  // exp(i pi t
   return make_double2(c, s);
 }
 
+// In-register FP64 DFT of size R by radix-2 decimation in time.
+template <int R>
+struct DftD {
+  __device__ __forceinline__ static void run(double2* x) {
+    double2 e[R / 2], o[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      e[i] = x[2 * i];
+      o[i] = x[2 * i + 1];
+    }
+    DftD<R / 2>::run(e);
+    DftD<R / 2>::run(o);
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) {
+      const double2 t = k == 0 ? o[k] : cmul(o[k], unit(-2.0 * (double)k / (double)R));
+      x[k] = make_double2(e[k].x + t.x, e[k].y + t.y);
+      x[k + R / 2] = make_double2(e[k].x - t.x, e[k].y - t.y);
+    }
+  }
+};
+template <>
+struct DftD<1> {
+  __device__ __forceinline__ static void run(double2*) {}
+};
+
 template <int R, bool FROM_REAL>
 __global__ void __launch_bounds__(kThreads) stockham_pass_fp64(const void* __restrict__ in_v,
                                                                double2* __restrict__ out, int64_t M, int64_t L) {
@@ -49,21 +77,10 @@ __global__ void __launch_bounds__(kThreads) stockham_pass_fp64(const void* __res
     }
     if (r > 0 && L > 1) a[r] = cmul(a[r], unit(-2.0 * (double)(r * j) / (double)(L * R)));
   }
-  double2 w[R];  // exp(-2 pi i m / R)
-#pragma unroll
-  for (int m = 0; m < R; ++m) w[m] = unit(-2.0 * (double)m / (double)R);
+  DftD<R>::run(a);
   const int64_t q = b / L;
 #pragma unroll
-  for (int rr = 0; rr < R; ++rr) {
-    double2 y = a[0];
-#pragma unroll
-    for (int r = 1; r < R; ++r) {
-      const double2 t = cmul(a[r], w[(r * rr) % R]);
-      y.x += t.x;
-      y.y += t.y;
-    }
-    out[j + L * (rr + (int64_t)R * q)] = y;
-  }
+  for (int rr = 0; rr < R; ++rr) out[j + L * (rr + (int64_t)R * q)] = a[rr];
 }
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
