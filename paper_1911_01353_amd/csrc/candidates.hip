@@ -3,28 +3,30 @@
 // that keeps only peaks above a user threshold).
 //
 // Row statistics: population mean and standard deviation per row, one read of
-// the row. Each thread folds 8 values at a time: their sum in FP64 is exact for
-// FP32 inputs, so the group mean and the group's sum of squared deviations are
-// formed directly, and groups are merged with the pairwise update of Chan,
-// Golub and LeVeque (1979). A constant row therefore gets a standard deviation
+// the row. Each thread folds 16 values at a time: the group mean is their FP64
+// sum over 16 and the group's squared deviations are formed directly; groups
+// are merged with the pairwise update of Chan, Golub and LeVeque (1979). A constant row therefore gets a standard deviation
 // of exactly 0. Chunks of a row are merged in a fixed order, so the result does
 // not depend on scheduling.
 //
 // Candidates: a point is kept when its power, widened to FP64, is strictly above
 // mean + k * sigma of its row, it is strictly greater than its left neighbour
 // and not less than its right one (row ends have no neighbour on that side).
-// Each wave appends its hits with one atomic add on the shared counter.
+// Hits are staged in LDS per workgroup and appended with one atomic add on the
+// shared counter per flush.
 #include "jerk_internal.h"
 
 namespace jerk {
 namespace {
 
 constexpr int kStatThreads = 256;
-constexpr int kStatPerThread = 8;
-constexpr int64_t kStatTile = kStatThreads * kStatPerThread;  // 2048 points
+constexpr int kStatPerThread = 16;                            // four float4 per thread
+constexpr int64_t kStatTile = kStatThreads * kStatPerThread;  // 4096 points
 constexpr int kPeakThreads = 256;
 constexpr int kPeakPerThread = 4;
 constexpr int64_t kPeakTile = kPeakThreads * kPeakPerThread;  // 1024 points
+constexpr int kPeakTilesPerBlock = 32;                        // a block scans 32768 points of a row
+constexpr int kStage = 2048;                                  // LDS candidate staging slots
 constexpr int kMaxGridY = 65535;
 
 struct Moments {
@@ -53,6 +55,9 @@ __device__ __forceinline__ Moments shfl_xor_moments(Moments v, int off) {
 }
 
 // grid (chunks, min(rows, 65535)); chunk c of a row covers [c * span, (c + 1) * span).
+// VEC: rows are 16-byte aligned (plane aligned, ld a multiple of 4), so a thread's
+// 16 values of a tile are four coalesced float4 loads; otherwise 16 scalar loads.
+template <bool VEC>
 __global__ void __launch_bounds__(kStatThreads) row_moments_kernel(const float* __restrict__ plane, int64_t ld,
                                                                    int32_t rows, int64_t n_r, int64_t span,
                                                                    Moments* __restrict__ part) {
@@ -65,28 +70,46 @@ __global__ void __launch_bounds__(kStatThreads) row_moments_kernel(const float* 
     Moments acc{0.0, 0.0, 0.0};
     for (int64_t base = lo; base < hi; base += kStatTile) {
       float v[kStatPerThread];
+      bool ok[kStatPerThread];
+#pragma unroll
+      for (int q = 0; q < kStatPerThread / 4; ++q) {
+        // element e = 4 (q * 256 + tid) + c of the tile
+        const int64_t p0 = base + 4 * ((int64_t)q * kStatThreads + threadIdx.x);
+        if (VEC && p0 + 3 < hi) {
+          const float4 f = *reinterpret_cast<const float4*>(src + p0);
+          v[4 * q + 0] = f.x;
+          v[4 * q + 1] = f.y;
+          v[4 * q + 2] = f.z;
+          v[4 * q + 3] = f.w;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) ok[4 * q + c] = true;
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            ok[4 * q + c] = p0 + c < hi;
+            v[4 * q + c] = ok[4 * q + c] ? src[p0 + c] : 0.0f;
+          }
+        }
+      }
       int cnt = 0;
       double sum = 0.0;
 #pragma unroll
-      for (int j = 0; j < kStatPerThread; ++j) {
-        const int64_t p = base + j * kStatThreads + threadIdx.x;
-        v[j] = 0.0f;
-        if (p < hi) {
-          v[j] = src[p];
-          sum += (double)v[j];
+      for (int e = 0; e < kStatPerThread; ++e) {
+        if (ok[e]) {
+          sum += (double)v[e];
           ++cnt;
         }
       }
       if (cnt > 0) {
         Moments g;
         g.n = (double)cnt;
-        g.m = sum / g.n;
+        g.m = cnt == kStatPerThread ? sum * (1.0 / kStatPerThread) : sum / g.n;
         g.m2 = 0.0;
 #pragma unroll
-        for (int j = 0; j < kStatPerThread; ++j) {
-          if (j * kStatThreads + threadIdx.x + base < hi) {
-            const double e = (double)v[j] - g.m;
-            g.m2 = fma(e, e, g.m2);
+        for (int e = 0; e < kStatPerThread; ++e) {
+          if (ok[e]) {
+            const double d = (double)v[e] - g.m;
+            g.m2 = fma(d, d, g.m2);
           }
         }
         acc = merge(acc, g);
@@ -119,49 +142,109 @@ __global__ void row_stats_finish_kernel(const Moments* __restrict__ part, int32_
   stats[2 * (int64_t)row + 1] = r.n > 0.0 ? sqrt(r.m2 / r.n) : 0.0;
 }
 
-// grid (ceil(n_r / 1024), min(rows, 65535)). Thread i of a block takes points
-// base + j * 256 + i, j = 0..3, so every load is coalesced; neighbours come from
-// the adjacent lanes, the wave's edge lanes read theirs.
+// grid (ceil(n_r / 32768), min(rows, 65535)). A block scans 32 tiles of 1024
+// points of a row, two tiles per step. In a tile, thread i takes the 4
+// consecutive points 4 i .. 4 i + 3 (one float4 load when rows are 16-byte
+// aligned) and reads their outer neighbours directly (cache hits), so no lane
+// exchange is needed. Hits are staged in LDS as (p, power) and flushed with one
+// atomic add on the shared counter per flush: two tiles hold at most 1024 peaks
+// (peaks are never adjacent), so the stage is flushed whenever fewer than 1024
+// of its slots are free.
+struct Staged {
+  uint32_t p;
+  float power;
+};
+
+template <bool VEC>
 __global__ void __launch_bounds__(kPeakThreads) find_candidates_kernel(
     const float* __restrict__ plane, int64_t ld, int32_t rows, int64_t n_r, const double* __restrict__ stats,
     double k_sigma, const int32_t* __restrict__ row_template, int32_t t_base, jerk_candidate* __restrict__ out,
     int64_t capacity, unsigned long long* __restrict__ count) {
+  __shared__ Staged stage[kStage];
+  __shared__ int n_stage;
+  __shared__ unsigned long long s_base;
   const int lane = threadIdx.x & 63;
   const uint64_t below = (1ull << lane) - 1ull;
-  for (int32_t row = blockIdx.y; row < rows; row += gridDim.y) {
-    const float* src = plane + (int64_t)row * ld;
-    const double mu = stats[2 * (int64_t)row];
-    const double sd = stats[2 * (int64_t)row + 1];
-    const double thr = mu + k_sigma * sd;
-    const uint32_t t = row_template ? (uint32_t)row_template[row] : (uint32_t)(t_base + row);
-#pragma unroll
-    for (int j = 0; j < kPeakPerThread; ++j) {
-      const int64_t p = (int64_t)blockIdx.x * kPeakTile + j * kPeakThreads + threadIdx.x;
-      const bool in = p < n_r;
-      const float v = in ? src[p] : 0.0f;
-      float left = __shfl_up(v, 1, 64);
-      float right = __shfl_down(v, 1, 64);
-      if (lane == 0 && in && p > 0) left = src[p - 1];
-      if (lane == 63 && p + 1 < n_r) right = src[p + 1];
-      const bool hit = in && (p == 0 || v > left) && (p + 1 == n_r || v >= right) && (double)v > thr;
-      const uint64_t mask = __ballot(hit);
-      if (mask == 0ull) continue;
-      const int leader = __ffsll((unsigned long long)mask) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(mask));
-      base = __shfl(base, leader, 64);
-      if (hit) {
-        const unsigned long long idx = base + (unsigned long long)__popcll(mask & below);
-        if (idx < (unsigned long long)capacity) {
-          jerk_candidate c;
-          c.t = t;
-          c.p = (uint32_t)p;
-          c.power = v;
-          c.sigma = (float)(((double)v - mu) / sd);
-          out[idx] = c;
-        }
+  if (threadIdx.x == 0) n_stage = 0;
+  __syncthreads();
+  double mu = 0.0, sd = 0.0;
+  uint32_t t = 0;
+  // Entered by all threads together. Every read of n_stage that decides a
+  // branch sits between two barriers, so all waves take the same branch.
+  auto flush = [&]() {
+    __syncthreads();  // every hit of the block is in the stage
+    const int n = n_stage;
+    __syncthreads();  // every thread has read n before it changes
+    if (n == 0) return;
+    if (threadIdx.x == 0) s_base = atomicAdd(count, (unsigned long long)n);
+    __syncthreads();
+    const unsigned long long b = s_base;
+    for (int i = threadIdx.x; i < n; i += kPeakThreads) {
+      if (b + (unsigned long long)i < (unsigned long long)capacity) {
+        const Staged e = stage[i];
+        jerk_candidate c;
+        c.t = t;
+        c.p = e.p;
+        c.power = e.power;
+        c.sigma = (float)(((double)e.power - mu) / sd);
+        out[b + i] = c;
       }
     }
+    __syncthreads();
+    if (threadIdx.x == 0) n_stage = 0;
+    __syncthreads();
+  };
+  for (int32_t row = blockIdx.y; row < rows; row += gridDim.y) {
+    const float* src = plane + (int64_t)row * ld;
+    mu = stats[2 * (int64_t)row];
+    sd = stats[2 * (int64_t)row + 1];
+    const double thr = mu + k_sigma * sd;
+    t = row_template ? (uint32_t)row_template[row] : (uint32_t)(t_base + row);
+    for (int tile = 0; tile < kPeakTilesPerBlock; tile += 2) {
+      const int64_t base = ((int64_t)blockIdx.x * kPeakTilesPerBlock + tile) * kPeakTile;
+      if (base >= n_r) break;  // uniform
+      float v[2][4], nb[2][2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int64_t p0 = base + u * kPeakTile + 4 * threadIdx.x;
+        if (VEC && p0 + 3 < n_r) {
+          const float4 f = *reinterpret_cast<const float4*>(src + p0);
+          v[u][0] = f.x;
+          v[u][1] = f.y;
+          v[u][2] = f.z;
+          v[u][3] = f.w;
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) v[u][c] = p0 + c < n_r ? src[p0 + c] : 0.0f;
+        }
+        nb[u][0] = p0 > 0 && p0 - 1 < n_r ? src[p0 - 1] : 0.0f;
+        nb[u][1] = p0 + 4 < n_r ? src[p0 + 4] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int64_t p0 = base + u * kPeakTile + 4 * threadIdx.x;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t p = p0 + c;
+          const float x = v[u][c];
+          const float left = c == 0 ? nb[u][0] : v[u][c - 1];
+          const float right = c == 3 ? nb[u][1] : v[u][c + 1];
+          const bool hit = p < n_r && (p == 0 || x > left) && (p + 1 == n_r || x >= right) && (double)x > thr;
+          const uint64_t mask = __ballot(hit);
+          if (mask == 0ull) continue;
+          const int leader = __ffsll((unsigned long long)mask) - 1;
+          int slot = 0;
+          if (lane == leader) slot = atomicAdd(&n_stage, __popcll(mask));
+          slot = __builtin_amdgcn_readlane(slot, leader);  // leader is wave-uniform
+          if (hit) stage[slot + __popcll(mask & below)] = Staged{(uint32_t)p, x};
+        }
+      }
+      __syncthreads();
+      const bool full = n_stage > kStage - (int)kPeakTile;
+      __syncthreads();
+      if (full) flush();
+    }
+    flush();
   }
 }
 
@@ -188,8 +271,13 @@ void plane_stats(const float* plane, int64_t ld, int32_t rows, int64_t n_r, doub
   const int64_t tiles = (n_r + kStatTile - 1) / kStatTile;
   const int64_t span = (tiles + chunks - 1) / chunks * kStatTile;
   const dim3 grid((unsigned)chunks, (unsigned)(rows < kMaxGridY ? rows : kMaxGridY));
-  hipLaunchKernelGGL(row_moments_kernel, grid, dim3(kStatThreads), 0, stream, plane, ld, rows, n_r, span,
-                     static_cast<Moments*>(ws));
+  const bool vec = (reinterpret_cast<uintptr_t>(plane) & 15u) == 0 && ld % 4 == 0;
+  if (vec)
+    hipLaunchKernelGGL(row_moments_kernel<true>, grid, dim3(kStatThreads), 0, stream, plane, ld, rows, n_r, span,
+                       static_cast<Moments*>(ws));
+  else
+    hipLaunchKernelGGL(row_moments_kernel<false>, grid, dim3(kStatThreads), 0, stream, plane, ld, rows, n_r, span,
+                       static_cast<Moments*>(ws));
   JERK_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(row_stats_finish_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream,
                      static_cast<const Moments*>(ws), rows, chunks, stats);
@@ -200,10 +288,16 @@ void find_candidates(const float* plane, int64_t ld, int32_t rows, int64_t n_r, 
                      double k_sigma, const int32_t* row_template, int32_t t_base, jerk_candidate* out,
                      int64_t capacity, unsigned long long* count, hipStream_t stream) {
   if (rows <= 0 || n_r <= 0) return;
-  const int64_t bx = (n_r + kPeakTile - 1) / kPeakTile;
+  const int64_t span = kPeakTile * kPeakTilesPerBlock;
+  const int64_t bx = (n_r + span - 1) / span;
   const dim3 grid((unsigned)bx, (unsigned)(rows < kMaxGridY ? rows : kMaxGridY));
-  hipLaunchKernelGGL(find_candidates_kernel, grid, dim3(kPeakThreads), 0, stream, plane, ld, rows, n_r, stats,
-                     k_sigma, row_template, t_base, out, capacity, count);
+  const bool vec = (reinterpret_cast<uintptr_t>(plane) & 15u) == 0 && ld % 4 == 0;
+  if (vec)
+    hipLaunchKernelGGL(find_candidates_kernel<true>, grid, dim3(kPeakThreads), 0, stream, plane, ld, rows, n_r,
+                       stats, k_sigma, row_template, t_base, out, capacity, count);
+  else
+    hipLaunchKernelGGL(find_candidates_kernel<false>, grid, dim3(kPeakThreads), 0, stream, plane, ld, rows, n_r,
+                       stats, k_sigma, row_template, t_base, out, capacity, count);
   JERK_HIP_CHECK(hipGetLastError());
 }
 
