@@ -137,11 +137,67 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
         for (int pp = 0; pp < P; ++pp)
           afr[r][q][pp] = (ks0 + q < KS) ? *frag_ptr(rb0 + r, ks0 + q, pp) : make_uint4(0, 0, 0, 0);
   };
-  if constexpr (RESIDENT) load_frags(0);
+  // Split-BF16 resident fragments are kept in the order the main loop visits
+  // k-steps: slot (part * 2 + parity) * NI + i holds k-step part * ksr + parity + 2 i.
+  // (FP16 keeps k-step order: its 32 resident slots leave no room for the
+  // fragment ring below.)
+  constexpr bool REUSE = RESIDENT && SPLIT;
+  constexpr int NI = KC / 4 > 0 ? KC / 4 : 1;
+  if constexpr (!REUSE && RESIDENT) load_frags(0);
+  if constexpr (REUSE) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int slot = 0; slot < KC; ++slot) {
+        const int part = slot / (2 * NI), parity = (slot / NI) % 2, i = slot % NI;
+        const int ksp = parity + 2 * i;
+#pragma unroll
+        for (int pp = 0; pp < P; ++pp)
+          afr[r][slot][pp] = ksp < ksr ? *frag_ptr(rb0 + r, part * ksr + ksp, pp) : make_uint4(0, 0, 0, 0);
+      }
+  }
 
   const int col = lane & 31;
   const int shift = col & 1;
   const int khalf = (lane >> 5) * 8;
+
+  // The spectrum operand of column tile c at k-step ks' (within a part) starts
+  // at window element 32 c + 16 ks' + col + khalf = 16 d + col + khalf with
+  // d = 2 c + ks': fragments depend on d only (Hankel structure).
+  auto load_b = [&](const uint32_t* lb, int part, int d, uint4& h, uint4& l) {
+    const int x = d * 16 + col + khalf;  // first element of this lane's 8
+    const int w0 = (x - shift) >> 1;     // word index in copy `shift`
+    const uint32_t* ph = lb + (part * 2 + shift) * WW + w0;
+    h = make_uint4(ph[0], ph[1], ph[2], ph[3]);
+    if constexpr (SPLIT) {
+      const uint32_t* pl = lb + ((part + 2) * 2 + shift) * WW + w0;
+      l = make_uint4(pl[0], pl[1], pl[2], pl[3]);
+    }
+  };
+  // The products of one k-step (tap fragments afr[.][q]), ordered so that
+  // consecutive MFMAs update different accumulators.
+  auto products = [&](int q, const uint4 (&bhi)[CT], const uint4 (&blo)[CT], f32x16 (&acc)[RB][CT]) {
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int prod = 0; prod < 3; ++prod)
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int c = 0; c < CT; ++c) {
+            const uint4 av = prod == 2 ? afr[r][q][1] : afr[r][q][0];
+            const uint4 bv = prod == 1 ? blo[c] : bhi[c];
+            acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                               __builtin_bit_cast(bf16x8, bv), acc[r][c], 0, 0, 0);
+          }
+    } else {
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, afr[r][q][0]),
+                                                            __builtin_bit_cast(f16x8, bhi[c]), acc[r][c], 0, 0, 0);
+    }
+  };
 
   // peak keys of this lane's rows (template 2q + lane/32 of each row block), over all its windows
   uint64_t best[KEYS ? RB : 1][4];
@@ -166,48 +222,45 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.f;
 
-    for (int ks0 = 0; ks0 < KS; ks0 += KC) {
-      if constexpr (!RESIDENT) load_frags(ks0);
+    if constexpr (REUSE) {
+      // k-steps of each part in two interleaved runs (even, then odd ks'):
+      // stepping ks' by 2 moves every column tile's fragment to the next tile's,
+      // so each step reads one new fragment from LDS instead of CT.
 #pragma unroll
-      for (int q = 0; q < KC; ++q) {
-        const int ks = ks0 + q;
-        if (ks >= KS) break;
-        const bool imag = ks >= ksr;
-        const int koff = (imag ? ks - ksr : ks) * 16 + khalf;
-        const int p_re = imag ? 1 : 0;
-        // B fragments of every column tile first, then the products ordered so
-        // that consecutive MFMAs update different accumulators.
-        uint4 bhi[CT], blo[CT];
+      for (int part = 0; part < 2; ++part)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-          const int x = c * 32 + col + koff;          // first element of this lane's 8
-          const int w0 = (x - shift) >> 1;             // word index in copy `shift`
-          const uint32_t* ph = lb + (p_re * 2 + shift) * WW + w0;
-          bhi[c] = make_uint4(ph[0], ph[1], ph[2], ph[3]);
-          if constexpr (SPLIT) {
-            const uint32_t* pl = lb + ((p_re + 2) * 2 + shift) * WW + w0;
-            blo[c] = make_uint4(pl[0], pl[1], pl[2], pl[3]);
+        for (int parity = 0; parity < 2; ++parity) {
+          if (parity >= ksr) continue;
+          uint4 bhi[CT], blo[CT];
+#pragma unroll
+          for (int c = 0; c < CT; ++c) load_b(lb, part, parity + 2 * c, bhi[c], blo[c]);
+#pragma unroll
+          for (int i = 0; i < NI; ++i) {
+            const int ksp = parity + 2 * i;
+            if (ksp >= ksr) break;
+            products((part * 2 + parity) * NI + i, bhi, blo, acc);
+            if (ksp + 2 < ksr) {
+#pragma unroll
+              for (int c = 0; c + 1 < CT; ++c) {
+                bhi[c] = bhi[c + 1];
+                blo[c] = blo[c + 1];
+              }
+              load_b(lb, part, ksp + 2 + 2 * (CT - 1), bhi[CT - 1], blo[CT - 1]);
+            }
           }
         }
-        if constexpr (SPLIT) {
+    } else {
+      for (int ks0 = 0; ks0 < KS; ks0 += KC) {
+        if constexpr (!RESIDENT) load_frags(ks0);
 #pragma unroll
-          for (int prod = 0; prod < 3; ++prod)
+        for (int q = 0; q < KC; ++q) {
+          const int ks = ks0 + q;
+          if (ks >= KS) break;
+          const int part = ks >= ksr ? 1 : 0;
+          uint4 bhi[CT], blo[CT];
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
-#pragma unroll
-              for (int c = 0; c < CT; ++c) {
-                const uint4 av = prod == 2 ? afr[r][q][1] : afr[r][q][0];
-                const uint4 bv = prod == 1 ? blo[c] : bhi[c];
-                acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
-                                                                   __builtin_bit_cast(bf16x8, bv), acc[r][c], 0, 0, 0);
-              }
-        } else {
-#pragma unroll
-          for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-              acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, afr[r][q][0]),
-                                                                __builtin_bit_cast(f16x8, bhi[c]), acc[r][c], 0, 0, 0);
+          for (int c = 0; c < CT; ++c) load_b(lb, part, ks - part * ksr + 2 * c, bhi[c], blo[c]);
+          products(q, bhi, blo, acc);
         }
       }
     }
@@ -368,12 +421,15 @@ void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream) {
   require(a.taps % 16 == 0 && a.taps >= 16 && a.taps <= 512, JERK_EINTERNAL, "GEMM taps out of range");
   const bool split = a.path != JERK_PATH_GEMM_FP16;
   // One row block (8 templates) per wave; the tap fragments of up to 128 taps
-  // (split) or 256 taps (FP16) stay in registers across windows.
+  // (split) or 256 taps (FP16) stay in registers across windows. Up to 64 taps
+  // (split) a wave covers 128 outputs per window (4 column tiles), which halves
+  // the window overhead per output.
   // window = 64 outputs + taps + 8 slack elements, loaded 64 per lane-step
   if (a.row_max) {
     // peak-key launches keep one row block per wave (room for the per-row keys)
     if (split) {
-      if (a.taps <= 128) launch_cfg<1, 2, 16, 4, true, true, true>(a, stream);
+      if (a.taps <= 64) launch_cfg<1, 4, 8, 4, true, true, true>(a, stream);
+      else if (a.taps <= 128) launch_cfg<1, 2, 16, 4, true, true, true>(a, stream);
       else if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false, true>(a, stream);
       else launch_cfg<1, 2, 8, 10, true, false, true>(a, stream);
     } else {
@@ -381,7 +437,8 @@ void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream) {
       else launch_cfg<1, 2, 16, 10, false, false, true>(a, stream);
     }
   } else if (split) {
-    if (a.taps <= 128) launch_cfg<1, 2, 16, 4, true, true, false>(a, stream);
+    if (a.taps <= 64) launch_cfg<1, 4, 8, 4, true, true, false>(a, stream);
+    else if (a.taps <= 128) launch_cfg<1, 2, 16, 4, true, true, false>(a, stream);
     else if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false, false>(a, stream);
     else launch_cfg<1, 2, 8, 10, true, false, false>(a, stream);
   } else {
