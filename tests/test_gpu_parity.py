@@ -22,7 +22,7 @@ TOL = {"fft": 1e-4, "split_bf16": 1e-4, "auto": 1e-4, "fp16": 1e-2}
 
 
 @pytest.fixture(scope="module")
-def c1():
+def small_search():
     cfg = synth.CONFIGS["bins2e15_z20_w60"]
     spec = synth.make_spectrum(cfg)
     grid = Grid(cfg.zmax, cfg.wmax, cfg.dz, cfg.dw)
@@ -30,8 +30,8 @@ def c1():
     return cfg, spec, grid, ora
 
 
-def test_templates_fp64_match_oracle(c1):
-    cfg, spec, grid, _ = c1
+def test_templates_fp64_match_oracle(small_search):
+    cfg, spec, grid, _ = small_search
     device()
     for zmax, wmax, sample in [(cfg.zmax, cfg.wmax, None), (300.0, 900.0, 12)]:
         plan = J.Plan(spec.shape[0], zmax, wmax, 2.0, 20.0, path="fft")
@@ -55,8 +55,8 @@ def test_templates_fp64_match_oracle(c1):
 
 
 @pytest.mark.parametrize("path", ["fft", "split_bf16", "fp16", "auto"])
-def test_full_plane_2e15_bins(c1, path):
-    cfg, spec, grid, ora = c1
+def test_full_plane_2e15_bins(small_search, path):
+    cfg, spec, grid, ora = small_search
     device()
     plan = J.Plan(spec.shape[0], cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
     bank = build_bank(plan)
@@ -69,8 +69,8 @@ def test_full_plane_2e15_bins(c1, path):
 
 
 @pytest.mark.parametrize("seg_len", [512, 1024, 2048, 4096])
-def test_fft_segment_length_invariance(c1, seg_len):
-    cfg, spec, grid, ora = c1
+def test_fft_segment_length_invariance(small_search, seg_len):
+    cfg, spec, grid, ora = small_search
     device()
     plan = J.Plan(spec.shape[0], cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path="fft", seg_len=seg_len)
     got = gpu_plane(plan, build_bank(plan), spec)
@@ -78,8 +78,8 @@ def test_fft_segment_length_invariance(c1, seg_len):
     assert s["max"] <= 1e-4, (seg_len, s)
 
 
-def test_fft_templates_per_block_is_bit_exact(c1):
-    cfg, spec, grid, _ = c1
+def test_fft_templates_per_block_is_bit_exact(small_search):
+    cfg, spec, grid, _ = small_search
     device()
     ref = None
     for tpb in (1, 3, 8, 64):
@@ -92,8 +92,8 @@ def test_fft_templates_per_block_is_bit_exact(c1):
 
 
 @pytest.mark.parametrize("path", ["fft", "split_bf16"])
-def test_template_slabs_match_full_plane(c1, path):
-    cfg, spec, grid, _ = c1
+def test_template_slabs_match_full_plane(small_search, path):
+    cfg, spec, grid, _ = small_search
     device()
     plan = J.Plan(spec.shape[0], cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
     bank = build_bank(plan)
@@ -180,10 +180,10 @@ def test_2e22_bins_sampled_windows():
 
 
 @pytest.mark.parametrize("path", ["fft", "split_bf16"])
-def test_member_slabs_match_full_plane(c1, path):
+def test_member_slabs_match_full_plane(small_search, path):
     """jerk_search_members: rows indexed by group member equal the full plane's rows (bit-exact)."""
     import torch
-    cfg, spec, grid, _ = c1
+    cfg, spec, grid, _ = small_search
     device()
     plan = J.Plan(spec.shape[0], cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
     bank = build_bank(plan)
