@@ -356,6 +356,24 @@ def harmonics_leg(J, torch, spec, n, reps=5):
     return res
 
 
+def cpu_host():
+    """Host CPU description and the worker count the CPU legs may use (at most 16)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count(), "affinity": avail, "workers": max(1, min(16, avail))}
+
+
 def cpu_baseline(spec, n_templates_sample):
     """The FP64 oracle, single-threaded, on full rows of a sample of templates."""
     import numpy as np
@@ -369,6 +387,73 @@ def cpu_baseline(spec, n_templates_sample):
     return {"value": pts / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(ts)} full rows (2^23 points each, templates {ts}) of the 2^22-bin search, "
                       f"FP64 numpy direct correlation incl. template quadrature, {dt:.1f} s"}
+
+
+_POOL_SPEC = None
+
+
+def _oracle_row(t):
+    from oracle import Grid, oracle_plane
+    return oracle_plane(_POOL_SPEC, Grid(200.0, 600.0, 2.0, 20.0), templates=[t]).size
+
+
+def cpu_oracle_pool(spec, n_rows, workers):
+    """The same FP64 oracle over a process pool, one worker per allowed host core."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import Grid
+    global _POOL_SPEC
+    _POOL_SPEC = spec
+    grid = Grid(200.0, 600.0, 2.0, 20.0)
+    ts = [int(t) for t in np.linspace(0, grid.n_templates - 1, n_rows)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        pts = sum(pool.map(_oracle_row, ts, chunksize=1))
+    dt = time.perf_counter() - t0
+    _POOL_SPEC = None
+    return {"value": pts / dt, "unit": "points/s", "cores": workers, "kind": "oracle_process_pool",
+            "sample": f"{len(ts)} full rows of the 2^22-bin search over {workers} processes, {dt:.1f} s"}
+
+
+def cpu_fft_overlap_save(spec, n_templates, workers):
+    """A CPU FFT search of the kind the paper compares with: FP32 overlap-save with scipy.fft on
+    all allowed cores, templates made beforehand (untimed). Taps come from the oracle."""
+    import numpy as np
+    import scipy.fft as sfft
+    from oracle import Grid, template_taps
+    grid = Grid(200.0, 600.0, 2.0, 20.0)
+    x = np.asarray(spec, dtype=np.complex64)
+    n = x.shape[0]
+    ts = [int(t) for t in np.linspace(0, grid.n_templates - 1, n_templates)]
+    total_t = 0.0
+    pts = 0
+    for t in ts:
+        zb, w, h = grid.params(t)
+        K = 2 * h
+        S = 1024
+        while S < 4 * K:
+            S *= 2
+        U = S - K + 1
+        c = np.zeros((2, S), dtype=np.complex128)
+        c[0, :K] = template_taps(zb, w, h, 0)
+        c[1, :K] = template_taps(zb, w, h, 1)
+        H = sfft.ifft(c, norm="forward").astype(np.complex64)
+        n_seg = -(-n // U)
+        xp = np.zeros(K // 2 - 1 + n_seg * U + S, dtype=np.complex64)
+        xp[K // 2 - 1: K // 2 - 1 + n] = x
+        idx = np.arange(n_seg)[:, None] * U + np.arange(S)[None, :]
+        t0 = time.perf_counter()
+        segs = xp[idx]
+        f = sfft.fft(segs, workers=workers)
+        row = np.empty(2 * n, dtype=np.float32)
+        for ph in (0, 1):
+            y = sfft.ifft(f * H[ph][None, :], workers=workers)[:, :U].reshape(-1)[:n]
+            row[ph::2] = (y.real * y.real + y.imag * y.imag)
+        total_t += time.perf_counter() - t0
+        pts += row.size
+    return {"value": pts / total_t, "unit": "points/s", "cores": workers, "kind": "fft_overlap_save_fp32_scipy",
+            "sample": f"{len(ts)} full rows of the 2^22-bin search (segments 1024..8192 >= 4K), {total_t:.1f} s"}
 
 
 def plane_errors(J, torch):
@@ -499,16 +584,24 @@ def main():
                                     "design notes; no multi-GPU path is built"}))
         sys.exit(2)
     import numpy as np
+
+    import synth
+
+    # The process-pool CPU leg forks workers, so it runs before anything touches the GPU.
+    cfg = synth.CONFIGS["bins2e22_z200_w600"]
+    spec_np = synth.make_spectrum(cfg)
+    host = cpu_host()
+    cpu_pool = None
+    if args.cpu_templates > 0:
+        cpu_pool = cpu_oracle_pool(spec_np, 2 * host["workers"], host["workers"])
+
     import torch
 
     import paper_1911_01353_amd as J
-    import synth
 
     J.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    cfg = synth.CONFIGS["bins2e22_z200_w600"]
-    spec_np = synth.make_spectrum(cfg)
     n = spec_np.shape[0]
     spec = torch.from_numpy(spec_np).cuda()
     print(f"[bench] spectrum {n} bins ready; path {args.path}", file=sys.stderr, flush=True)
@@ -592,6 +685,11 @@ def main():
         batch = batch_leg(J, torch, args.batch_items)
         print(f"[bench] batch {batch['points_per_s']:.3e} points/s", file=sys.stderr, flush=True)
     cpu = cpu_baseline(spec_np, args.cpu_templates) if args.cpu_templates > 0 else None
+    cpu_fft = None
+    if args.cpu_templates > 0:
+        cpu_fft = cpu_fft_overlap_save(spec_np, 16, host["workers"])
+        print(f"[bench] CPU: oracle {cpu['value']:.2e}, oracle pool {cpu_pool['value']:.2e}, "
+              f"FFT overlap-save {cpu_fft['value']:.2e} points/s", file=sys.stderr, flush=True)
 
     line = {
         "metric": "(r,z,w) plane points/s, FP32 vs split-BF16 @<=1e-4 rel err; p50/p99 latency",
@@ -613,6 +711,9 @@ def main():
                    "nbins": n, "templates": T, "points_per_step": points_per_step},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cpu_host": host,
+        "cpu_oracle_all_cores": cpu_pool,
+        "cpu_fft_overlap_save": cpu_fft,
         "paths_points_per_s": paths,
         "vs_unfused_rocfft": rocfft,
         "candidate_selection": cands,

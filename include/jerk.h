@@ -70,6 +70,11 @@ const char* jerk_status_str(int32_t status);
 const char* jerk_last_error(void);
 /* Library version string, e.g. "jerk-mi355x 1.0 gfx950". */
 const char* jerk_version(void);
+/* State of the work queued on `stream` so far, without blocking: JERK_OK when it has all
+ * finished without error, JERK_EPENDING while some of it still runs, JERK_EHIP (text in
+ * jerk_last_error) when the device reported an error. Asynchronous kernel faults of the other
+ * entry points surface here or at the caller's next synchronisation. */
+int32_t jerk_stream_check(hipStream_t stream);
 
 /* ---- plans -------------------------------------------------------------- */
 typedef struct jerk_plan jerk_plan;

@@ -17,7 +17,7 @@ from ._lib import (JERK_EAGAIN, JERK_ECANCELED, JERK_EHIP, JERK_EINVAL, JERK_ENO
                    PATH_AUTO, PATH_FFT_FP32, PATH_GEMM_FP16, PATH_GEMM_SPLIT_BF16, PATH_NAMES, JerkError)
 
 __all__ = [
-    "Plan", "Server", "peaks_reduce", "stats_workspace_bytes", "plane_stats", "find_candidates",
+    "Plan", "Server", "peaks_reduce", "stream_check", "stats_workspace_bytes", "plane_stats", "find_candidates",
     "candidates_numpy", "CANDIDATE_DTYPE", "spectrum_workspace_bytes", "prepare_spectrum", "JERK_EHIP", "JERK_ECANCELED", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
     "PATH_AUTO", "PATH_NAMES", "JERK_OK", "JERK_EINVAL", "JERK_ENOMEM", "JERK_EAGAIN", "JERK_EPENDING",
 ]
@@ -30,6 +30,16 @@ def load():
 
 def version() -> str:
     return _lib.load().jerk_version().decode()
+
+
+def stream_check(stream=None) -> int:
+    """``jerk_stream_check``: JERK_OK when the stream's work has finished, JERK_EPENDING while it
+    runs; raises JerkError on a device error."""
+    st = _lib.load().jerk_stream_check(_stream_ptr(stream))
+    if st == JERK_EPENDING:
+        return st
+    _lib.check(st)
+    return st
 
 
 def _stream_ptr(stream) -> C.c_void_p:

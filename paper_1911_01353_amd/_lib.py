@@ -131,6 +131,7 @@ SIGNATURES = {
                                       C.c_void_p, C.c_size_t, C.c_uint32, C.c_void_p]),
     "jerk_peaks_reduce": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
     "jerk_stats_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int64]),
+    "jerk_stream_check": (C.c_int32, [C.c_void_p]),
     "jerk_spectrum_workspace_bytes": (C.c_size_t, [C.c_int64]),
     "jerk_harmonic_shape": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "jerk_harmonic_sum": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_void_p, C.c_int64,

@@ -160,6 +160,19 @@ const char* jerk_last_error(void) { return jerk::g_last_error.c_str(); }
 
 const char* jerk_version(void) { return "jerk-mi355x 1.0 gfx950"; }
 
+int32_t jerk_stream_check(hipStream_t stream) {
+  int32_t pending = 0;
+  const int32_t st = guarded([&] {
+    const hipError_t e = hipStreamQuery(stream);
+    if (e == hipErrorNotReady) {
+      pending = 1;
+      return;
+    }
+    JERK_HIP_CHECK(e);
+  });
+  return st == JERK_OK && pending ? JERK_EPENDING : st;
+}
+
 int32_t jerk_plan_create(const jerk_plan_desc* desc, jerk_plan** out) {
   return guarded([&] {
     require(desc != nullptr && out != nullptr, JERK_EINVAL, "desc and out must not be NULL");

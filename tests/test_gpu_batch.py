@@ -115,3 +115,22 @@ def test_batch_rejects_mixed_paths():
     with pytest.raises(J.JerkError) as ei:
         plan.batch_search(bank, [(spec, plane, None)], ws)
     assert ei.value.status == J.JERK_EINVAL
+
+
+def test_stream_check_reports_finished_work():
+    import torch
+    import synth
+    dev = device()
+    cfg = synth.CONFIGS["bins2e15_z20_w60"]
+    spec = torch.from_numpy(synth.make_spectrum(cfg)).to(dev)
+    n = spec.shape[0]
+    plan = J.Plan(n, cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path="fft")
+    bank = plan.new_bank()
+    plan.build_templates(bank)
+    T = plan.info()["n_templates"]
+    plane = torch.empty((T, 2 * n), dtype=torch.float32, device=dev)
+    plan.search(bank, spec, plane, 0, T)
+    assert J.stream_check() in (J.JERK_OK, J.JERK_EPENDING)
+    torch.cuda.synchronize()
+    assert J.stream_check() == J.JERK_OK
+    plan.close()
