@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--cand-sigma", type=float, default=6.0, help="candidate threshold in row sigmas")
     ap.add_argument("--harm-templates", type=int, default=1,
                     help="time harmonic sums (H = 2, 4, 8) over a 147-template plane of the 2^22-bin spectrum")
+    ap.add_argument("--prep", type=int, default=1,
+                    help="time the device spectrum preparation of a 2^23-sample series")
     ap.add_argument("--save-plan", default="", help="write the main plan's per-group configuration (JSON)")
     ap.add_argument("--load-plan", default="", help="use a saved per-group configuration instead of autotuning")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -325,6 +327,26 @@ def candidates_leg(J, torch, plan, bank, spec, n, rows, k_sigma, reps=5):
             "stats_GBps": 4 * pts / t_stats / 1e9, "candidates_GBps": 4 * pts / t_cand / 1e9,
             "stats_hbm_frac": 4 * pts / t_stats / 1e9 / HBM_PEAK_GBS,
             "candidates_hbm_frac": 4 * pts / t_cand / 1e9 / HBM_PEAK_GBS}
+
+
+def spectrum_leg(J, torch, n_samples, reps=5):
+    """Device spectrum preparation (FP64) of an N(0,1) series of n_samples float32 samples;
+    algorithmic bytes: 4 B per sample read + 8 B per bin written."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(191106)
+    x = torch.randn(n_samples, generator=g, device="cuda", dtype=torch.float32)
+    out, ws = J.prepare_spectrum(x)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        J.prepare_spectrum(x, out=out, ws=ws)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+    by = 4 * n_samples + 8 * (n_samples // 2)
+    return {"n_samples": n_samples, "ms": t * 1e3, "samples_per_s": n_samples / t, "GBps": by / t / 1e9,
+            "hbm_frac": by / t / 1e9 / HBM_PEAK_GBS}
 
 
 def harmonics_leg(J, torch, spec, n, reps=5):
@@ -671,6 +693,10 @@ def main():
               f"(stats {cands['stats_GBps']:.0f} GB/s, peaks {cands['candidates_GBps']:.0f} GB/s)",
               file=sys.stderr, flush=True)
     harm = harmonics_leg(J, torch, spec, n) if args.harm_templates else None
+    prep = spectrum_leg(J, torch, 2 * n) if args.prep else None
+    if prep:
+        print(f"[bench] spectrum preparation {prep['ms']:.3f} ms for {prep['n_samples']} samples",
+              file=sys.stderr, flush=True)
     if harm:
         print(f"[bench] harmonic sums: " + ", ".join(f"H={h[1:]} {v['GBps']:.0f} GB/s" for h, v in harm.items()
                                                        if h.startswith("H")), file=sys.stderr, flush=True)
@@ -718,6 +744,7 @@ def main():
         "vs_unfused_rocfft": rocfft,
         "candidate_selection": cands,
         "harmonic_sums": harm,
+        "spectrum_preparation": prep,
         "plane_error_2e15_bins": errors,
         "template_build_s": main_res["t_build"],
         "autotune_s": main_res["t_tune"],
