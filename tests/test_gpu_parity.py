@@ -201,3 +201,42 @@ def test_member_slabs_match_full_plane(small_search, path):
             torch.cuda.synchronize()
             got = slab.cpu().numpy()
             assert np.array_equal(got.view(np.uint32), full[ms[m0:m1]].view(np.uint32)), (g, m0, m1)
+
+
+_WIDE_ORACLE = {}
+
+
+def _wide_oracle(spec, grid, ts):
+    key = tuple(ts)
+    if key not in _WIDE_ORACLE:
+        _WIDE_ORACLE[key] = oracle_plane(spec, grid, templates=list(ts))
+    return _WIDE_ORACLE[key]
+
+
+@pytest.mark.parametrize("path", ["fft", "split_bf16", "fp16"])
+def test_widest_templates_zmax300(path):
+    """The widest width groups of a zmax 300, wmax 900 grid (up to 496 taps; the serving
+    workload's widest) on a 2^15-bin spectrum, against the oracle."""
+    import torch
+    dev = device()
+    rng = np.random.default_rng(300)
+    n = 1 << 15
+    spec = ((rng.standard_normal(n) + 1j * rng.standard_normal(n)) / np.sqrt(2)).astype(np.complex64)
+    grid = Grid(300.0, 900.0, 2.0, 20.0)
+    plan = J.Plan(n, 300.0, 900.0, 2.0, 20.0, path=path)
+    bank = build_bank(plan)
+    groups = plan.groups()
+    members = plan.members()
+    assert max(g["taps"] for g in groups) >= 480
+    x = torch.from_numpy(spec).to(dev)
+    for g in (len(groups) - 1, len(groups) - 3):
+        gi = groups[g]
+        m = min(4, gi["n_members"])
+        slab = torch.full((m, 2 * n), float("nan"), dtype=torch.float32, device=dev)
+        plan.search_members(bank, x, slab, g, 0, m)
+        torch.cuda.synchronize()
+        got = slab.cpu().numpy()
+        ts = [int(t) for t in members[gi["first_member"]: gi["first_member"] + m]]
+        ora = _wide_oracle(spec, grid, ts)
+        assert error_summary(got, ora)["max"] <= TOL[path], (g, gi["taps"])
+    plan.close()
