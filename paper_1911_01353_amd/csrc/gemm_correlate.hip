@@ -59,13 +59,13 @@ __host__ __device__ constexpr int window_cols() { return 32 * CT; }
 // group and a run of consecutive windows of 32*CT outputs. Tap fragments for up
 // to KC k-steps stay in registers; the spectrum window is double-buffered in
 // LDS and the next window's loads are issued before the current window's MFMAs.
-template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT, bool KEYS>
+template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT, bool KEYS, int KT>
 __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64_t windows_per_wg, int64_t n_colchunks) {
   extern __shared__ uint32_t lds32[];
   constexpr int P = SPLIT ? 2 : 1;        // parts of each operand (hi, lo)
   constexpr int NPART = 2 * P;            // LDS part arrays (re/im x hi/lo)
   constexpr int COLS = window_cols<CT>();
-  const int K = a.taps;
+  const int K = KT > 0 ? KT : a.taps;  // KT > 0: the tap count is a compile-time constant
   const int hg = K / 2;
   const int KS = 2 * K / 16;   // k-steps of the real-expanded contraction
   const int ksr = K / 16;      // k-steps over the real parts
@@ -206,6 +206,32 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
 #pragma unroll
     for (int q = 0; q < 4; ++q) best[r][q] = 0;
 
+  // Output row of each of this lane's templates (2q + lane/32 of each row
+  // block), -1 when it is outside the requested range; fixed for all windows.
+  int64_t orow_of[RB][4];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m_local = (tblk * RB + r) * 8 + 2 * q + (lane >> 5);
+      int64_t orow = -1;
+      if (m_local < n_members) {
+        const int t = a.members[a.m_begin + m_local];
+        const int64_t o =
+            a.row_by_member ? (int64_t)(a.m_begin + m_local - a.row_base) : (int64_t)(t - a.t_begin);
+        // o < 0: below the requested member range (same block of 8)
+        if (t >= a.t_begin && t < a.t_end && o >= 0) orow = o;
+      }
+      orow_of[r][q] = orow;
+    }
+
+  // Wait here for the loop-invariant loads above (resident tap fragments, member
+  // rows). Otherwise the first use inside the window loop waits on the vector
+  // memory counter, which by then also counts the previous window's plane
+  // stores and the next window's loads, and every window stalls on them.
+  // 0x0F70: vmcnt 0, expcnt and lgkmcnt unconstrained.
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+
   load_window(win_first);
   store_window(0);
   __syncthreads();
@@ -270,12 +296,8 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
     for (int r = 0; r < RB; ++r) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m_local = (tblk * RB + r) * 8 + 2 * q + (lane >> 5);
-        if (m_local >= n_members) continue;
-        const int t = a.members[a.m_begin + m_local];
-        if (t < a.t_begin || t >= a.t_end) continue;
-        const int64_t orow = a.row_by_member ? (int64_t)(a.m_begin + m_local - a.row_base) : (int64_t)(t - a.t_begin);
-        if (orow < 0) continue;  // below the requested member range (same block of 8)
+        const int64_t orow = orow_of[r][q];
+        if (orow < 0) continue;
         float2* __restrict__ row = a.plane ? reinterpret_cast<float2*>(a.plane + orow * a.ld) + col0 : nullptr;
         const int lim = (int)min((int64_t)COLS, a.nbins - col0);
 #pragma unroll
@@ -312,14 +334,8 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
           const uint64_t o = __shfl_xor(k, off, 64);
           k = o > k ? o : k;
         }
-        const int m_local = (tblk * RB + r) * 8 + 2 * q + (lane >> 5);
-        if ((lane & 31) == 0 && m_local < n_members) {
-          const int t = a.members[a.m_begin + m_local];
-          const int64_t orow =
-              a.row_by_member ? (int64_t)(a.m_begin + m_local - a.row_base) : (int64_t)(t - a.t_begin);
-          if (t >= a.t_begin && t < a.t_end && orow >= 0)
-            atomicMax(reinterpret_cast<unsigned long long*>(a.row_max + orow), (unsigned long long)k);
-        }
+        if ((lane & 31) == 0 && orow_of[r][q] >= 0)
+          atomicMax(reinterpret_cast<unsigned long long*>(a.row_max + orow_of[r][q]), (unsigned long long)k);
       }
   }
 }
@@ -393,8 +409,9 @@ void gemm_bank_build(const Plan& p, const Group& g, const double2* taps, void* o
 
 namespace {
 
-template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT, bool KEYS>
+template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT, bool KEYS, int KT = 0>
 void launch_cfg(const GemmArgs& a, hipStream_t stream) {
+  require(KT == 0 || a.taps == KT, JERK_EINTERNAL, "GEMM kernel built for another tap count");
   const int n_members = a.m_end - a.m_begin;
   constexpr int COLS = window_cols<CT>();
   const int64_t n_win = (a.nbins + COLS - 1) / COLS;
@@ -408,11 +425,28 @@ void launch_cfg(const GemmArgs& a, hipStream_t stream) {
   require(COLS + a.taps + 8 <= 64 * MAXLD, JERK_EINTERNAL, "GEMM window larger than the per-lane load budget");
   require(!RESIDENT || 2 * a.taps / 16 <= KC, JERK_EINTERNAL, "resident tap fragments exceed the register budget");
   const size_t lds = (size_t)2 * (SPLIT ? 4 : 2) * 2 * win_words(COLS, a.taps) * sizeof(uint32_t);
-  hipLaunchKernelGGL((gemm_correlate_kernel<RB, CT, KC, MAXLD, SPLIT, RESIDENT, KEYS>), dim3((unsigned)blocks), dim3(64), lds, stream, a,
+  hipLaunchKernelGGL((gemm_correlate_kernel<RB, CT, KC, MAXLD, SPLIT, RESIDENT, KEYS, KT>), dim3((unsigned)blocks), dim3(64), lds, stream, a,
                      windows_per_wg, n_colchunks);
 }
 
 }  // namespace
+
+// Split-BF16 groups of up to 128 taps: one kernel per tap count, so the k-step
+// runs unroll completely and the fragment ring lives in fixed registers. Up to
+// 96 taps a wave covers 4 column tiles (128 outputs) per window.
+template <bool KEYS>
+void launch_split_resident(const GemmArgs& a, hipStream_t stream) {
+  switch (a.taps) {
+    case 16: launch_cfg<1, 4, 4, 4, true, true, KEYS, 16>(a, stream); break;
+    case 32: launch_cfg<1, 4, 4, 4, true, true, KEYS, 32>(a, stream); break;
+    case 48: launch_cfg<1, 4, 8, 4, true, true, KEYS, 48>(a, stream); break;
+    case 64: launch_cfg<1, 4, 8, 4, true, true, KEYS, 64>(a, stream); break;
+    case 80: launch_cfg<1, 4, 12, 4, true, true, KEYS, 80>(a, stream); break;
+    case 96: launch_cfg<1, 4, 12, 4, true, true, KEYS, 96>(a, stream); break;
+    case 112: launch_cfg<1, 2, 16, 4, true, true, KEYS, 112>(a, stream); break;
+    default: launch_cfg<1, 2, 16, 4, true, true, KEYS, 128>(a, stream); break;
+  }
+}
 
 void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream) {
   const int n_members = a.m_end - a.m_begin;
@@ -421,15 +455,12 @@ void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream) {
   require(a.taps % 16 == 0 && a.taps >= 16 && a.taps <= 512, JERK_EINTERNAL, "GEMM taps out of range");
   const bool split = a.path != JERK_PATH_GEMM_FP16;
   // One row block (8 templates) per wave; the tap fragments of up to 128 taps
-  // (split) or 256 taps (FP16) stay in registers across windows. Up to 64 taps
-  // (split) a wave covers 128 outputs per window (4 column tiles), which halves
-  // the window overhead per output.
+  // (split) or 256 taps (FP16) stay in registers across windows.
   // window = 64 outputs + taps + 8 slack elements, loaded 64 per lane-step
   if (a.row_max) {
     // peak-key launches keep one row block per wave (room for the per-row keys)
     if (split) {
-      if (a.taps <= 64) launch_cfg<1, 4, 8, 4, true, true, true>(a, stream);
-      else if (a.taps <= 128) launch_cfg<1, 2, 16, 4, true, true, true>(a, stream);
+      if (a.taps <= 128) launch_split_resident<true>(a, stream);
       else if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false, true>(a, stream);
       else launch_cfg<1, 2, 8, 10, true, false, true>(a, stream);
     } else {
@@ -437,8 +468,7 @@ void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream) {
       else launch_cfg<1, 2, 16, 10, false, false, true>(a, stream);
     }
   } else if (split) {
-    if (a.taps <= 64) launch_cfg<1, 4, 8, 4, true, true, false>(a, stream);
-    else if (a.taps <= 128) launch_cfg<1, 2, 16, 4, true, true, false>(a, stream);
+    if (a.taps <= 128) launch_split_resident<false>(a, stream);
     else if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false, false>(a, stream);
     else launch_cfg<1, 2, 8, 10, true, false, false>(a, stream);
   } else {
