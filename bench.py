@@ -62,6 +62,8 @@ def parse():
                     help="time harmonic sums (H = 2, 4, 8) over a 147-template plane of the 2^22-bin spectrum")
     ap.add_argument("--prep", type=int, default=1,
                     help="time the device spectrum preparation of a 2^23-sample series")
+    ap.add_argument("--small-reps", type=int, default=200,
+                    help="time the 2^15-bin search per repetition inside a graph of this many (0 = skip)")
     ap.add_argument("--save-plan", default="", help="write the main plan's per-group configuration (JSON)")
     ap.add_argument("--load-plan", default="", help="use a saved per-group configuration instead of autotuning")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -327,6 +329,50 @@ def candidates_leg(J, torch, plan, bank, spec, n, rows, k_sigma, reps=5):
             "stats_GBps": 4 * pts / t_stats / 1e9, "candidates_GBps": 4 * pts / t_cand / 1e9,
             "stats_hbm_frac": 4 * pts / t_stats / 1e9 / HBM_PEAK_GBS,
             "candidates_hbm_frac": 4 * pts / t_cand / 1e9 / HBM_PEAK_GBS}
+
+
+def small_search_leg(J, torch, reps=200):
+    """The 2^15-bin search (147 templates, 9.6e6 points) on each path, timed per repetition
+    inside a captured graph of `reps` searches (launch overhead excluded)."""
+    import synth
+    cfg = synth.CONFIGS["bins2e15_z20_w60"]
+    spec = torch.from_numpy(synth.make_spectrum(cfg)).cuda()
+    n = spec.shape[0]
+    res = {"workload": "2^15 bins, zmax 20, wmax 60 (147 templates), plane in HBM", "reps": reps}
+    for path in ("fft", "split_bf16", "fp16", "auto"):
+        plan = J.Plan(n, cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
+        if path in ("fft", "auto"):
+            plan.autotune(spec)
+        bank = plan.new_bank()
+        plan.build_templates(bank)
+        T = plan.info()["n_templates"]
+        out = torch.empty((T, 2 * n), dtype=torch.float32, device="cuda")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plan.search(bank, spec, out, 0, T)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(reps):
+                plan.search(bank, spec, out, 0, T)
+        g.replay()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        g.replay()
+        ev[1].record()
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+        pts = T * 2 * n
+        res[path] = {"us_per_search": t * 1e6, "points_per_s": pts / t,
+                     "groups": [{"taps": g["taps"], "path": ["fft", "split_bf16", "fp16"][g["path"]],
+                                 "seg_len": g["seg_len"], "templates_per_block": g["templates_per_block"]}
+                                for g in plan.groups()]}
+        del g, out, bank
+        plan.close()
+    return res
 
 
 def spectrum_leg(J, torch, n_samples, reps=5):
@@ -694,6 +740,11 @@ def main():
               file=sys.stderr, flush=True)
     harm = harmonics_leg(J, torch, spec, n) if args.harm_templates else None
     prep = spectrum_leg(J, torch, 2 * n) if args.prep else None
+    small = small_search_leg(J, torch, args.small_reps) if args.small_reps > 0 else None
+    if small:
+        print("[bench] 2^15-bin search per graph rep: " + ", ".join(
+            f"{p} {small[p]['us_per_search']:.1f} us" for p in ("fft", "split_bf16", "fp16", "auto")), file=sys.stderr,
+            flush=True)
     if prep:
         print(f"[bench] spectrum preparation {prep['ms']:.3f} ms for {prep['n_samples']} samples",
               file=sys.stderr, flush=True)
@@ -745,6 +796,7 @@ def main():
         "candidate_selection": cands,
         "harmonic_sums": harm,
         "spectrum_preparation": prep,
+        "search_2e15_bins_graph": small,
         "plane_error_2e15_bins": errors,
         "template_build_s": main_res["t_build"],
         "autotune_s": main_res["t_tune"],

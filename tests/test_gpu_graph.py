@@ -1,0 +1,52 @@
+"""jerk_search inside a captured graph: every replay equals the eager plane bit for bit.
+
+The search path enqueues kernels only (no memset, allocation or synchronisation), so
+a caller may capture it. The graph is replayed several times with eager library work
+and synchronisations in between, and each replay is checked.
+"""
+
+import numpy as np
+import pytest
+
+import paper_1911_01353_amd as J
+import synth
+
+from gpu_helpers import build_bank, device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("path", ["fft", "split_bf16", "fp16"])
+def test_graph_replays_match_eager(path, small_spectrum):
+    import torch
+    dev = device()
+    cfg = synth.CONFIGS["bins2e15_z20_w60"]
+    n = small_spectrum.shape[0]
+    plan = J.Plan(n, cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
+    bank = build_bank(plan)
+    T = plan.info()["n_templates"]
+    spec = torch.from_numpy(small_spectrum).to(dev)
+    eager = torch.empty((T, 2 * n), dtype=torch.float32, device=dev)
+    plan.search(bank, spec, eager, 0, T)
+    torch.cuda.synchronize()
+    want = eager.cpu().numpy()
+    out = torch.full((T, 2 * n), float("nan"), dtype=torch.float32, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.search(bank, spec, out, 0, T)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.search(bank, spec, out, 0, T)
+    other = torch.empty_like(eager)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), want.view(np.uint32)), (path, rep)
+        plan.search(bank, spec, other, 0, T)  # eager work between replays
+        torch.cuda.synchronize()
+    plan.close()
