@@ -276,7 +276,8 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
           }
         }
     } else {
-      for (int ks0 = 0; ks0 < KS; ks0 += KC) {
+#pragma unroll
+      for (int ks0 = 0; ks0 < (KT > 0 ? 2 * KT / 16 : KS); ks0 += KC) {
         if constexpr (!RESIDENT) load_frags(ks0);
 #pragma unroll
         for (int q = 0; q < KC; ++q) {
@@ -434,6 +435,27 @@ void launch_cfg(const GemmArgs& a, hipStream_t stream) {
 // Split-BF16 groups of up to 128 taps: one kernel per tap count, so the k-step
 // runs unroll completely and the fragment ring lives in fixed registers. Up to
 // 96 taps a wave covers 4 column tiles (128 outputs) per window.
+// Split-BF16 groups of more than 128 taps, tap fragments streamed in chunks of
+// 8 k-steps. Up to 240 taps one kernel per tap count, so the chunk loop unrolls
+// and the fragment loads can be issued early.
+template <bool KEYS>
+void launch_split_streamed(const GemmArgs& a, hipStream_t stream) {
+  switch (a.taps) {
+    case 144: launch_cfg<1, 2, 8, 6, true, false, KEYS, 144>(a, stream); break;
+    case 160: launch_cfg<1, 2, 8, 6, true, false, KEYS, 160>(a, stream); break;
+    case 176: launch_cfg<1, 2, 8, 6, true, false, KEYS, 176>(a, stream); break;
+    case 192: launch_cfg<1, 2, 8, 6, true, false, KEYS, 192>(a, stream); break;
+    case 208: launch_cfg<1, 2, 8, 6, true, false, KEYS, 208>(a, stream); break;
+    case 224: launch_cfg<1, 2, 8, 6, true, false, KEYS, 224>(a, stream); break;
+    case 240: launch_cfg<1, 2, 8, 6, true, false, KEYS, 240>(a, stream); break;
+    // wider: the generic streamed kernels (fully unrolled, these would spill)
+    default:
+      if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false, KEYS>(a, stream);
+      else launch_cfg<1, 2, 8, 10, true, false, KEYS>(a, stream);
+      break;
+  }
+}
+
 template <bool KEYS>
 void launch_split_resident(const GemmArgs& a, hipStream_t stream) {
   switch (a.taps) {
@@ -461,16 +483,14 @@ void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream) {
     // peak-key launches keep one row block per wave (room for the per-row keys)
     if (split) {
       if (a.taps <= 128) launch_split_resident<true>(a, stream);
-      else if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false, true>(a, stream);
-      else launch_cfg<1, 2, 8, 10, true, false, true>(a, stream);
+      else launch_split_streamed<true>(a, stream);
     } else {
       if (a.taps <= 256) launch_cfg<1, 2, 32, 6, false, true, true>(a, stream);
       else launch_cfg<1, 2, 16, 10, false, false, true>(a, stream);
     }
   } else if (split) {
     if (a.taps <= 128) launch_split_resident<false>(a, stream);
-    else if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false, false>(a, stream);
-    else launch_cfg<1, 2, 8, 10, true, false, false>(a, stream);
+    else launch_split_streamed<false>(a, stream);
   } else {
     if (a.taps <= 256) launch_cfg<1, 2, 32, 6, false, true, false>(a, stream);
     else launch_cfg<1, 2, 16, 10, false, false, false>(a, stream);
