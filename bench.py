@@ -47,7 +47,7 @@ def parse():
                     help="templates (full rows) in the oracle's timed sample; 0 skips cpu_baseline")
     ap.add_argument("--errors", type=int, default=1, help="measure plane errors on the 2^15-bin search")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the plan before timing (untimed)")
-    ap.add_argument("--serve-requests", type=int, default=24,
+    ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests per serving pass (cold then warm template cache); 0 skips serving")
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load (arrival rate / service rate)")
     ap.add_argument("--batch-items", type=int, default=256,
