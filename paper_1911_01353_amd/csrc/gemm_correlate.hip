@@ -276,8 +276,8 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
           }
         }
     } else {
-#pragma unroll
-      for (int ks0 = 0; ks0 < (KT > 0 ? 2 * KT / 16 : KS); ks0 += KC) {
+      // one chunk of KC k-steps: its tap fragments (streamed), then its products
+      auto chunk = [&](int ks0) {
         if constexpr (!RESIDENT) load_frags(ks0);
 #pragma unroll
         for (int q = 0; q < KC; ++q) {
@@ -289,6 +289,12 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
           for (int c = 0; c < CT; ++c) load_b(lb, part, ks - part * ksr + 2 * c, bhi[c], blo[c]);
           products(q, bhi, blo, acc);
         }
+      };
+      if constexpr (KT > 0) {
+#pragma unroll
+        for (int ks0 = 0; ks0 < 2 * KT / 16; ks0 += KC) chunk(ks0);
+      } else {
+        for (int ks0 = 0; ks0 < KS; ks0 += KC) chunk(ks0);
       }
     }
     // ---- epilogue: |Y|^2 for both phases, one float2 per (template, k0) ----
