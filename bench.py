@@ -637,9 +637,18 @@ def batch_leg(J, torch, n_items, slab_rows=128):
         plan.batch_search(bank, items, ws, t_b, min(T, t_b + slab_rows), graph=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # the same slabs as one flat launch each (a workgroup per tile), also graph-replayed
+    plan.batch_search(bank, items, ws, 0, min(T, slab_rows), graph=True, flat=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t_b in range(0, T, slab_rows):
+        plan.batch_search(bank, items, ws, t_b, min(T, t_b + slab_rows), graph=True, flat=True)
+    torch.cuda.synchronize()
+    wall_flat = time.perf_counter() - t0
     seg = plan.group(0)["seg_len"]
     plan.close()
     return {"items": n_items, "templates": T, "points": pts, "wall_s": wall, "points_per_s": pts / wall,
+            "flat_wall_s": wall_flat, "flat_points_per_s": pts / wall_flat,
             "seg_len": seg, "autotune_s": t_tune, "launches": -(-T // slab_rows),
             "workload": "synth.batch_spectra_specs(256, seed 191103) lengths; GPU noise spectra; zmax 100, wmax 300"}
 
@@ -760,7 +769,8 @@ def main():
     batch = None
     if args.batch_items > 0:
         batch = batch_leg(J, torch, args.batch_items)
-        print(f"[bench] batch {batch['points_per_s']:.3e} points/s", file=sys.stderr, flush=True)
+        print(f"[bench] batch {batch['points_per_s']:.3e} points/s (persistent), "
+              f"{batch['flat_points_per_s']:.3e} (flat)", file=sys.stderr, flush=True)
     cpu = cpu_baseline(spec_np, args.cpu_templates) if args.cpu_templates > 0 else None
     cpu_fft = None
     if args.cpu_templates > 0:

@@ -196,6 +196,8 @@ typedef struct jerk_batch_item {
 } jerk_batch_item;
 
 #define JERK_BATCH_GRAPH 1u /* capture the launch in a hipGraph on first use and replay it */
+#define JERK_BATCH_FLAT 2u  /* one flat launch (a workgroup per tile, the hardware dispatcher balancing
+                               the load) instead of the persistent kernel; same results bit for bit */
 
 /* Workspace bytes jerk_batch_search needs for up to `count` items. */
 size_t jerk_batch_workspace_bytes(const jerk_plan* plan, int32_t count);

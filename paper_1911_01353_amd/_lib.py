@@ -71,6 +71,7 @@ class Peak(C.Structure):
 
 
 BATCH_GRAPH = 1
+BATCH_FLAT = 2
 SERVE_DRYRUN = 1
 
 

@@ -24,8 +24,9 @@ struct BatchCtx {
   hipGraphExec_t exec = nullptr;
   const void* graph_ws = nullptr;
   const void* graph_tw = nullptr;
-  int32_t graph_seg = 0, graph_ept = 0, graph_grid = 0;
-  bool graph_keys = false;
+  int32_t graph_seg = 0, graph_ept = 0;
+  int64_t graph_grid = 0;
+  bool graph_keys = false, graph_flat = false;
   int32_t grid_cache_seg = 0, grid_cache_ept = 0, grid_cache = 0;
 };
 
@@ -82,7 +83,8 @@ void batch_search(Plan& p, const void* d_bank, const jerk_batch_item* items, int
   require(d_bank != nullptr, JERK_EINVAL, "bank must not be NULL");
   require(count >= 0 && (count == 0 || items != nullptr), JERK_EINVAL, "items must not be NULL");
   require(0 <= t_begin && t_begin <= t_end && t_end <= p.T, JERK_EINVAL, "template range outside [0, n_templates]");
-  require((flags & ~JERK_BATCH_GRAPH) == 0, JERK_EINVAL, "unknown flags");
+  require((flags & ~(JERK_BATCH_GRAPH | JERK_BATCH_FLAT)) == 0, JERK_EINVAL, "unknown flags");
+  const bool flat = (flags & JERK_BATCH_FLAT) != 0;
   const auto var = uniform_variant(p);
   const int32_t seg = var.first, ept = var.second;
   const size_t need = jobs_capacity_bytes(p, count);
@@ -182,21 +184,24 @@ void batch_search(Plan& p, const void* d_bank, const jerk_batch_item* items, int
   if (!(flags & JERK_BATCH_GRAPH)) {
     JERK_HIP_CHECK(hipMemcpyAsync(ws, c.pinned, bytes, hipMemcpyHostToDevice, stream));
     JERK_HIP_CHECK(hipEventRecord(c.staged, stream));
-    fft_persistent_launch(d_jobs, d_hdr, seg, ept, keys, tw, grid, stream);
+    if (flat) fft_multi_launch(d_jobs, d_hdr, total, seg, ept, keys, tw, stream);
+    else fft_persistent_launch(d_jobs, d_hdr, seg, ept, keys, tw, grid, stream);
     return;
   }
   // Graph path: the graph holds the counter reset and the persistent kernel;
   // its arguments (workspace, twiddles, grid) fix the graph, the job table does not.
-  const int32_t ggrid = c.grid_cache;  // full-size grid so one graph serves any tile count
+  // (persistent: a full-size grid, so one graph serves any tile count; flat: the grid is the tile count)
+  const int64_t ggrid = flat ? total : c.grid_cache;
   if (!c.exec || c.graph_ws != d_ws || c.graph_tw != tw || c.graph_seg != seg || c.graph_ept != ept ||
-      c.graph_grid != ggrid || c.graph_keys != keys) {
+      c.graph_grid != ggrid || c.graph_keys != keys || c.graph_flat != flat) {
     if (c.exec) JERK_HIP_CHECK(hipGraphExecDestroy(c.exec));
     if (c.graph) JERK_HIP_CHECK(hipGraphDestroy(c.graph));
     c.exec = nullptr;
     c.graph = nullptr;
     JERK_HIP_CHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
     try {
-      fft_persistent_launch(d_jobs, d_hdr, seg, ept, keys, tw, ggrid, c.stream);
+      if (flat) fft_multi_launch(d_jobs, d_hdr, ggrid, seg, ept, keys, tw, c.stream);
+      else fft_persistent_launch(d_jobs, d_hdr, seg, ept, keys, tw, (int32_t)ggrid, c.stream);
     } catch (...) {
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(c.stream, &g);
@@ -211,6 +216,7 @@ void batch_search(Plan& p, const void* d_bank, const jerk_batch_item* items, int
     c.graph_ept = ept;
     c.graph_keys = keys;
     c.graph_grid = ggrid;
+    c.graph_flat = flat;
   }
   JERK_HIP_CHECK(hipEventRecord(c.ev_in, stream));
   JERK_HIP_CHECK(hipStreamWaitEvent(c.stream, c.ev_in, 0));

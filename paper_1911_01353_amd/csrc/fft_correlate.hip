@@ -332,6 +332,27 @@ __global__ void __launch_bounds__(S / E) fft_persistent_kernel(const FftJob* __r
   }
 }
 
+// One launch over a job table, one workgroup per tile (grid = total tiles):
+// workgroup i takes tile i, the hardware dispatcher balancing the load.
+template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS>
+__global__ void __launch_bounds__(S / E) fft_multi_kernel(const FftJob* __restrict__ jobs,
+                                                          const BatchHeader* __restrict__ hdr,
+                                                          const float2* __restrict__ tw) {
+  __shared__ float2 lds[S + S / 16];
+  __shared__ uint64_t red[8];
+  const int64_t tile = blockIdx.x;
+  const int n_jobs = hdr->n_jobs;
+  int lo = 0, hi = n_jobs - 1;  // last job with tile_begin <= tile
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tile_begin <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const FftJob& j = jobs[lo];
+  const int64_t local = tile - j.tile_begin;
+  fft_tile<S, E, R1, R2, R3, R4, KEYS>(j, local % j.n_seg, (int)(local / j.n_seg), lds, red, tw);
+}
+
 __global__ void batch_reset_kernel(BatchHeader* hdr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) hdr->counter = 0ull;
 }
@@ -416,6 +437,25 @@ void fft_persistent_launch(const FftJob* d_jobs, BatchHeader* d_hdr, int32_t seg
     else                                                                                                          \
       hipLaunchKernelGGL((fft_persistent_kernel<S, E, A, B, C, D, false>), dim3(grid), dim3(S / E), 0, stream,    \
                          d_jobs, d_hdr, twiddles);                                                                \
+    JERK_HIP_CHECK(hipGetLastError());                                                                            \
+    return;                                                                                                       \
+  }
+  JERK_FFT_VARIANTS(X)
+#undef X
+  throw Error(JERK_EINTERNAL, "unsupported FFT kernel variant");
+}
+
+void fft_multi_launch(const FftJob* d_jobs, const BatchHeader* d_hdr, int64_t total, int32_t seg_len, int32_t ept,
+                      bool keys, const float2* twiddles, hipStream_t stream) {
+  require(total >= 1 && total < (int64_t(1) << 31), JERK_EINVAL, "batch too large for one flat launch");
+#define X(S, E, A, B, C, D)                                                                                       \
+  if (seg_len == S && ept == E) {                                                                                 \
+    if (keys)                                                                                                     \
+      hipLaunchKernelGGL((fft_multi_kernel<S, E, A, B, C, D, true>), dim3((unsigned)total), dim3(S / E), 0,       \
+                         stream, d_jobs, d_hdr, twiddles);                                                        \
+    else                                                                                                          \
+      hipLaunchKernelGGL((fft_multi_kernel<S, E, A, B, C, D, false>), dim3((unsigned)total), dim3(S / E), 0,      \
+                         stream, d_jobs, d_hdr, twiddles);                                                        \
     JERK_HIP_CHECK(hipGetLastError());                                                                            \
     return;                                                                                                       \
   }

@@ -122,6 +122,9 @@ int64_t fft_job_tiles(FftJob& j, int32_t seg_len);
 bool fft_variant_supported(int32_t seg_len, int32_t ept);
 void fft_correlate_launch(FftJob j, int32_t seg_len, int32_t ept, const float2* twiddles, hipStream_t stream);
 // keys: the jobs write peak keys (every job's row_max set) - selects the kernel instantiation.
+// One flat launch over a job table: grid = total tiles, workgroup i takes tile i.
+void fft_multi_launch(const FftJob* d_jobs, const BatchHeader* d_hdr, int64_t total, int32_t seg_len, int32_t ept,
+                      bool keys, const float2* twiddles, hipStream_t stream);
 void fft_persistent_launch(const FftJob* d_jobs, BatchHeader* d_hdr, int32_t seg_len, int32_t ept, bool keys,
                            const float2* twiddles, int32_t grid, hipStream_t stream);
 // Workgroups of the persistent kernel that fit on the current device at once.

@@ -28,7 +28,7 @@ def _row_peaks(plane):
     return plane[np.arange(plane.shape[0]), idx], idx
 
 
-def _run_batch(plan, bank, specs_np, graph, t_begin, t_end, with_keys=True, ws=None):
+def _run_batch(plan, bank, specs_np, graph, t_begin, t_end, with_keys=True, ws=None, flat=False):
     import torch
     dev = device()
     rows = t_end - t_begin
@@ -38,7 +38,7 @@ def _run_batch(plan, bank, specs_np, graph, t_begin, t_end, with_keys=True, ws=N
             else None for s in specs_np]
     if ws is None:
         ws = torch.empty(plan.batch_workspace_bytes(len(specs)), dtype=torch.uint8, device=dev)
-    plan.batch_search(bank, list(zip(specs, planes, keys)), ws, t_begin, t_end, graph=graph)
+    plan.batch_search(bank, list(zip(specs, planes, keys)), ws, t_begin, t_end, graph=graph, flat=flat)
     torch.cuda.synchronize()
     out = []
     for s, pl, k in zip(specs_np, planes, keys):
@@ -60,12 +60,13 @@ def plan_bank():
     return plan, build_bank(plan)
 
 
+@pytest.mark.parametrize("flat", [False, True])
 @pytest.mark.parametrize("graph", [False, True])
-def test_batch_matches_single_searches(plan_bank, graph):
+def test_batch_matches_single_searches(plan_bank, graph, flat):
     plan, bank = plan_bank
     specs = _spectra(LENGTHS, 11)
     T = plan.info()["n_templates"]
-    res = _run_batch(plan, bank, specs, graph, 0, T)
+    res = _run_batch(plan, bank, specs, graph, 0, T, flat=flat)
     for s, (pl, (pw, pp)) in zip(specs, res):
         ref = gpu_plane(plan, bank, s)
         assert not np.isnan(pl).any()
@@ -84,8 +85,10 @@ def test_batch_template_slab_and_oracle(plan_bank):
         assert error_summary(pl, ora)["max"] <= 1e-4
 
 
-def test_graph_replays_match_eager(plan_bank):
-    """Replays of one captured graph with new job tables, with eager work in between."""
+@pytest.mark.parametrize("flat", [False, True])
+def test_graph_replays_match_eager(plan_bank, flat):
+    """Replays of captured graphs with new job tables, with eager work in between (the persistent
+    launch keeps one graph; the flat launch captures again when the tile count changes)."""
     import torch
     plan, bank = plan_bank
     T = plan.info()["n_templates"]
@@ -97,7 +100,7 @@ def test_graph_replays_match_eager(plan_bank):
         # unrelated eager work on the same stream between replays
         junk = torch.randn(1 << 20, device=dev)
         _ = (junk * 2).sum().item()
-        got = _run_batch(plan, bank, specs, True, 0, T, ws=ws)
+        got = _run_batch(plan, bank, specs, True, 0, T, ws=ws, flat=flat)
         want = _run_batch(plan, bank, specs, False, 0, T)
         for (a, pa), (b, pb) in zip(got, want):
             assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
