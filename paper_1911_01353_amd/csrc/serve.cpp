@@ -5,7 +5,7 @@
 // per-template peak keys and peaks) fits, and are cut into work units (a
 // width group's member range over all segments). Each launch slot (its own
 // stream) takes units round-robin from every admitted request up to a tile
-// budget: FFT units run in one persistent launch over a job table, MFMA units
+// budget: FFT units run in one flat launch over a job table, MFMA units
 // as direct launches. So requests that arrive while others run share the
 // next launches with them instead of waiting behind them. A request's result
 // is the per-template maximum over its tiles (an atomicMax of order-free
@@ -146,7 +146,7 @@ struct jerk_server {
   bool stop = false;
   uint64_t next_ticket = 1, use_clock = 0;
   std::chrono::steady_clock::time_point t0;
-  int32_t grid_seg = 0, grid_ept = 0, grid = 0;
+
   int64_t fail_launch_at = 0, fail_build_at = 0, launch_count = 0, build_count = 0;
   bool paused = false;  // admission held (test hook)
   jerk_serve_stats st{};
@@ -408,7 +408,7 @@ bool dispatch(jerk_server& s, Slot& sl) {
 
   for (auto& e : taken) JERK_HIP_CHECK(hipStreamWaitEvent(sl.stream, e.first->ready, 0));
   if (!jobs.empty()) {
-    // one persistent launch per segment length present (normally one)
+    // one launch per segment length present (normally one)
     std::map<std::pair<int32_t, int32_t>, std::vector<FftJob>> by_seg;
     std::map<int32_t, const float2*> tw_of;
     for (auto& e : jobs) by_seg[e.second].push_back(e.first);
@@ -437,13 +437,9 @@ bool dispatch(jerk_server& s, Slot& sl) {
       std::memcpy(pinned + poff, &h, sizeof(h));
       std::memcpy(pinned + poff + 256, js.data(), js.size() * sizeof(FftJob));
       JERK_HIP_CHECK(hipMemcpyAsync(dtab + poff, pinned + poff, bytes, hipMemcpyHostToDevice, sl.stream));
-      if (s.grid_seg != seg || s.grid_ept != ept) {
-        s.grid = fft_persistent_grid(seg, ept);
-        s.grid_seg = seg;
-        s.grid_ept = ept;
-      }
-      fft_persistent_launch(reinterpret_cast<const FftJob*>(dtab + poff + 256), reinterpret_cast<BatchHeader*>(dtab + poff),
-                            seg, ept, true, tw_of[seg], (int32_t)std::min<int64_t>(s.grid, total), sl.stream);
+      // one flat launch over the units of every request taken (a workgroup per tile)
+      fft_multi_launch(reinterpret_cast<const FftJob*>(dtab + poff + 256), reinterpret_cast<BatchHeader*>(dtab + poff),
+                       total, seg, ept, true, tw_of[seg], sl.stream);
       poff += align_up(bytes);
     }
   }
