@@ -176,7 +176,8 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
   };
   // The products of one k-step (tap fragments afr[.][q]), ordered so that
   // consecutive MFMAs update different accumulators.
-  auto products = [&](int q, const uint4 (&bhi)[CT], const uint4 (&blo)[CT], f32x16 (&acc)[RB][CT]) {
+  auto products_with = [&](const uint4 (&A)[RB][KC][P], int q, const uint4 (&bhi)[CT], const uint4 (&blo)[CT],
+                           f32x16 (&acc)[RB][CT]) {
     if constexpr (SPLIT) {
 #pragma unroll
       for (int prod = 0; prod < 3; ++prod)
@@ -184,7 +185,7 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
         for (int r = 0; r < RB; ++r)
 #pragma unroll
           for (int c = 0; c < CT; ++c) {
-            const uint4 av = prod == 2 ? afr[r][q][1] : afr[r][q][0];
+            const uint4 av = prod == 2 ? A[r][q][1] : A[r][q][0];
             const uint4 bv = prod == 1 ? blo[c] : bhi[c];
             acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
                                                                __builtin_bit_cast(bf16x8, bv), acc[r][c], 0, 0, 0);
@@ -194,9 +195,12 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
       for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int c = 0; c < CT; ++c)
-          acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, afr[r][q][0]),
+          acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, A[r][q][0]),
                                                             __builtin_bit_cast(f16x8, bhi[c]), acc[r][c], 0, 0, 0);
     }
+  };
+  auto products = [&](int q, const uint4 (&bhi)[CT], const uint4 (&blo)[CT], f32x16 (&acc)[RB][CT]) {
+    products_with(afr, q, bhi, blo, acc);
   };
 
   // peak keys of this lane's rows (template 2q + lane/32 of each row block), over all its windows
@@ -290,7 +294,43 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
           products(q, bhi, blo, acc);
         }
       };
-      if constexpr (KT > 0) {
+      if constexpr (KT > 0 && !RESIDENT && KT <= (KEYS ? 160 : 192)) {
+        // Two chunk buffers: the next chunk's tap fragments load while this
+        // chunk's MFMAs run (the tap count is a compile-time constant, so the
+        // buffer of every chunk is fixed). Wider groups would spill.
+        constexpr int KST = 2 * KT / 16;
+        constexpr int NCH = (KST + KC - 1) / KC;
+        uint4 abuf[2][RB][KC][P];
+        auto load_into = [&](uint4 (&A)[RB][KC][P], int ks0) {
+#pragma unroll
+          for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int q = 0; q < KC; ++q)
+#pragma unroll
+              for (int pp = 0; pp < P; ++pp)
+                A[r][q][pp] = (ks0 + q < KST) ? *frag_ptr(rb0 + r, ks0 + q, pp) : make_uint4(0, 0, 0, 0);
+        };
+        load_into(abuf[0], 0);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          if (ch + 1 < NCH) {
+            load_into(abuf[(ch + 1) & 1], (ch + 1) * KC);
+            // keep the loads here: the scheduler would otherwise sink each one to
+            // just before its MFMA, leaving its latency exposed
+            __builtin_amdgcn_sched_barrier(0);
+          }
+#pragma unroll
+          for (int q = 0; q < KC; ++q) {
+            const int ks = ch * KC + q;
+            if (ks >= KST) break;
+            const int part = ks >= ksr ? 1 : 0;
+            uint4 bhi[CT], blo[CT];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) load_b(lb, part, ks - part * ksr + 2 * c, bhi[c], blo[c]);
+            products_with(abuf[ch & 1], q, bhi, blo, acc);
+          }
+        }
+      } else if constexpr (KT > 0) {
 #pragma unroll
         for (int ks0 = 0; ks0 < 2 * KT / 16; ks0 += KC) chunk(ks0);
       } else {
@@ -446,14 +486,16 @@ void launch_cfg(const GemmArgs& a, hipStream_t stream) {
 // and the fragment loads can be issued early.
 template <bool KEYS>
 void launch_split_streamed(const GemmArgs& a, hipStream_t stream) {
+  // chunks of 4 k-steps where the two chunk buffers fit in registers, else 8
+  constexpr bool K = KEYS;
   switch (a.taps) {
-    case 144: launch_cfg<1, 2, 8, 6, true, false, KEYS, 144>(a, stream); break;
-    case 160: launch_cfg<1, 2, 8, 6, true, false, KEYS, 160>(a, stream); break;
-    case 176: launch_cfg<1, 2, 8, 6, true, false, KEYS, 176>(a, stream); break;
-    case 192: launch_cfg<1, 2, 8, 6, true, false, KEYS, 192>(a, stream); break;
-    case 208: launch_cfg<1, 2, 8, 6, true, false, KEYS, 208>(a, stream); break;
-    case 224: launch_cfg<1, 2, 8, 6, true, false, KEYS, 224>(a, stream); break;
-    case 240: launch_cfg<1, 2, 8, 6, true, false, KEYS, 240>(a, stream); break;
+    case 144: launch_cfg<1, 2, 4, 6, true, false, K, 144>(a, stream); break;
+    case 160: launch_cfg<1, 2, 4, 6, true, false, K, 160>(a, stream); break;
+    case 176: launch_cfg<1, 2, K ? 8 : 4, 6, true, false, K, 176>(a, stream); break;
+    case 192: launch_cfg<1, 2, K ? 8 : 4, 6, true, false, K, 192>(a, stream); break;
+    case 208: launch_cfg<1, 2, 8, 6, true, false, K, 208>(a, stream); break;
+    case 224: launch_cfg<1, 2, 8, 6, true, false, K, 224>(a, stream); break;
+    case 240: launch_cfg<1, 2, 8, 6, true, false, K, 240>(a, stream); break;
     // wider: the generic streamed kernels (fully unrolled, these would spill)
     default:
       if (a.taps <= 256) launch_cfg<1, 2, 8, 6, true, false, KEYS>(a, stream);
