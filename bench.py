@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--cand-rows", type=int, default=512,
                     help="plane rows of the 2^22-bin search timed through candidate selection (0 = skip)")
     ap.add_argument("--cand-sigma", type=float, default=6.0, help="candidate threshold in row sigmas")
+    ap.add_argument("--fused-reps", type=int, default=3,
+                    help="time the whole search with fused candidate selection (no plane) this many times "
+                         "(0 = skip)")
     ap.add_argument("--harm-templates", type=int, default=1,
                     help="time harmonic sums (H = 2, 4, 8) over a 147-template plane of the 2^22-bin spectrum")
     ap.add_argument("--prep", type=int, default=1,
@@ -329,6 +332,47 @@ def candidates_leg(J, torch, plan, bank, spec, n, rows, k_sigma, reps=5):
             "stats_GBps": 4 * pts / t_stats / 1e9, "candidates_GBps": 4 * pts / t_cand / 1e9,
             "stats_hbm_frac": 4 * pts / t_stats / 1e9 / HBM_PEAK_GBS,
             "candidates_hbm_frac": 4 * pts / t_cand / 1e9 / HBM_PEAK_GBS}
+
+
+def search_candidates_leg(J, torch, spec, n, k_sigma, reps=3):
+    """The whole search (every template) with candidate selection fused in: no plane is written.
+    FFT path, autotuned plan (untimed). Speculative level 0.9 (1 + k) (the noise rows' thresholds lie
+    near 1 + k on a unit-mean-power spectrum), staging slots sized by the library from that level.
+    Timed with events around the whole call, median of `reps`."""
+    import numpy as np
+    plan = J.Plan(n, 200.0, 600.0, 2.0, 20.0, path="fft")
+    plan.autotune(spec)
+    bank = plan.new_bank()
+    plan.build_templates(bank)
+    T = plan.info()["n_templates"]
+    groups = plan.groups()
+    pre = 0.9 * (1.0 + k_sigma)
+    ws = torch.empty(plan.search_candidates_workspace_bytes(n, pre, 0, T), dtype=torch.uint8, device="cuda")
+    cap = 1 << 26
+    out = torch.empty((cap, 4), dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    stats = torch.empty((T, 2), dtype=torch.float64, device="cuda")
+    times = []
+    for i in range(reps + 1):
+        count.zero_()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.search_candidates(bank, spec, k_sigma, pre, out, count, 0, T, stats=stats, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        if i:
+            times.append(e0.elapsed_time(e1) * 1e-3)
+    t = float(np.median(times))
+    pts = 2 * n * T
+    found = int(count.item())
+    mean_sigma = stats.mean(dim=0).cpu().tolist()
+    ws_bytes = ws.numel()
+    del out, ws, bank
+    plan.close()
+    return {"templates": T, "points": pts, "k_sigma": k_sigma, "pre_level": pre, "workspace_bytes": ws_bytes,
+            "candidates": found, "ms": t * 1e3, "ms_all": [x * 1e3 for x in times], "points_per_s": pts / t,
+            "row_mean_sigma_avg": mean_sigma}
 
 
 def small_search_leg(J, torch, reps=200):
@@ -747,6 +791,17 @@ def main():
         print(f"[bench] candidate selection {cands['points_per_s']:.3e} points/s "
               f"(stats {cands['stats_GBps']:.0f} GB/s, peaks {cands['candidates_GBps']:.0f} GB/s)",
               file=sys.stderr, flush=True)
+    fused = None
+    if args.fused_reps > 0:
+        fused = search_candidates_leg(J, torch, spec, n, args.cand_sigma, args.fused_reps)
+        two_step = None
+        if cands and "fft" in paths:
+            two_step = 1.0 / (1.0 / paths["fft"] + 1.0 / cands["points_per_s"])
+            fused["two_step_fft_points_per_s"] = two_step
+            fused["speedup_vs_two_step"] = fused["points_per_s"] / two_step
+        print(f"[bench] search with fused candidate selection {fused['points_per_s']:.3e} points/s "
+              f"({fused['ms']:.1f} ms, {fused['candidates']} candidates)"
+              + (f", two-step {two_step:.3e}" if two_step else ""), file=sys.stderr, flush=True)
     harm = harmonics_leg(J, torch, spec, n) if args.harm_templates else None
     prep = spectrum_leg(J, torch, 2 * n) if args.prep else None
     small = small_search_leg(J, torch, args.small_reps) if args.small_reps > 0 else None
@@ -804,6 +859,7 @@ def main():
         "paths_points_per_s": paths,
         "vs_unfused_rocfft": rocfft,
         "candidate_selection": cands,
+        "search_with_candidates": fused,
         "harmonic_sums": harm,
         "spectrum_preparation": prep,
         "search_2e15_bins_graph": small,

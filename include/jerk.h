@@ -302,6 +302,42 @@ int32_t jerk_find_candidates(const float* d_plane, int64_t ld, int32_t rows, int
                              jerk_candidate* d_out, int64_t capacity, unsigned long long* d_count,
                              hipStream_t stream);
 
+/* ---- search with candidate selection, no plane ---------------------------------
+ * The matched filter of jerk_search and the selection of jerk_plane_stats +
+ * jerk_find_candidates in one call that never writes the plane (the paper times the
+ * filter together with this selection, section "Results"). Rows [t_begin, t_end), every
+ * width group in the range on the FFT path.
+ *
+ * The threshold mean + k_sigma * sigma of a row is known only after the whole row, so the
+ * call runs per width group: a speculative pass that accumulates each row's sum and sum
+ * of squares (FP64) and stages the peaks above pre_level in a run of slots per tile
+ * (tile = FFT segment x template block), a tile's excess going to a shared pool of half
+ * the slots; row statistics; the staged peaks above their row's threshold; the points at
+ * segment ends; and an exact pass that recomputes the rows whose threshold lies below
+ * pre_level or that lost a staged peak to a full pool.
+ * The candidates are therefore the same for any pre_level and `staged`; those two only
+ * set the cost. A good pre_level sits a little below the lowest row threshold expected:
+ * for a spectrum normalised to unit mean power the noise powers are close to exponential
+ * with mean and sigma near 1, so thresholds lie near 1 + k_sigma and e.g.
+ * 0.9 (1 + k_sigma) leaves the exact pass idle.
+ *
+ * staged: slots per tile; 0 = 2 exp(-pre_level) of the tile's points + 16 (the expected
+ * share above pre_level on a unit-mean-power spectrum is exp(-pre_level)) and 2^16 more
+ * pool entries.
+ * d_stats: (mean, sigma) of row t at d_stats[2 (t - t_begin)] (device, FP64), or NULL.
+ * Candidates are appended to d_out as by jerk_find_candidates (t = template index, count
+ * in *d_count, which the caller clears first; order unspecified; capacity overflow counted).
+ * EINVAL for a bad range, nbins outside [1, 2^31), non-finite k_sigma or pre_level, a
+ * negative staged or capacity, or NULL pointers; EUNSUPPORTED when a group in the range
+ * is on an MFMA path; ENOMEM for a workspace smaller than
+ * jerk_search_candidates_workspace_bytes (0 for invalid arguments). Asynchronous on stream. */
+size_t jerk_search_candidates_workspace_bytes(const jerk_plan* plan, int64_t nbins, int32_t t_begin, int32_t t_end,
+                                              double pre_level, int64_t staged);
+int32_t jerk_search_candidates(const jerk_plan* plan, const void* d_bank, const void* d_spec, int64_t nbins,
+                               int32_t t_begin, int32_t t_end, double k_sigma, double pre_level, int64_t staged,
+                               double* d_stats, jerk_candidate* d_out, int64_t capacity,
+                               unsigned long long* d_count, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- serving: continuous batching of search requests ----------------------- */
 typedef struct jerk_server jerk_server;
 

@@ -213,6 +213,40 @@ class Plan:
         _lib.check(_lib.load().jerk_harmonic_shape(self.handle, n_r, n_harm, C.byref(zf), C.byref(wf), C.byref(pf)))
         return zf.value, wf.value, pf.value
 
+    def search_candidates_workspace_bytes(self, nbins: int, pre_level: float, t_begin: int = 0,
+                                          t_end: int | None = None, staged: int = 0) -> int:
+        if t_end is None:
+            t_end = self.info()["n_templates"]
+        return int(_lib.load().jerk_search_candidates_workspace_bytes(self.handle, nbins, t_begin, t_end,
+                                                                      float(pre_level), staged))
+
+    def search_candidates(self, bank, spec, k_sigma: float, pre_level: float, out, count, t_begin: int = 0,
+                          t_end: int | None = None, staged: int = 0, stats=None, ws=None, stream=None):
+        """Enqueue ``jerk_search_candidates``: the search of rows [t_begin, t_end) with candidate
+        selection and no plane. ``out``: (capacity, 4) int32 device tensor of jerk_candidate records;
+        ``count``: one-element int64 device tensor the caller zeroes first; ``staged``: staging slots
+        per tile (0 = automatic); ``stats``: optional (rows, 2) float64 device tensor of row (mean,
+        sigma). ``ws`` is allocated here when omitted; returns it so that the caller can keep it
+        alive with the stream."""
+        import torch
+        if spec.dtype != torch.complex64 or spec.dim() != 1 or not spec.is_contiguous():
+            raise ValueError("spec must be a contiguous 1-D complex64 tensor")
+        if out.dim() != 2 or out.shape[1] != 4 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous (capacity, 4) tensor")
+        n = spec.shape[0]
+        if t_end is None:
+            t_end = self.info()["n_templates"]
+        if stats is not None and (not stats.is_contiguous() or stats.shape[0] < t_end - t_begin):
+            raise ValueError("stats must be a contiguous (rows, 2) float64 tensor")
+        need = self.search_candidates_workspace_bytes(n, pre_level, t_begin, t_end, staged)
+        if ws is None:
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=spec.device)
+        _lib.check(_lib.load().jerk_search_candidates(
+            self.handle, _dev_ptr(bank), _dev_ptr(spec), n, t_begin, t_end, float(k_sigma), float(pre_level),
+            int(staged), _dev_ptr(stats) if stats is not None else None, _dev_ptr(out), out.shape[0],
+            _dev_ptr(count), _dev_ptr(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)))
+        return ws
+
     def harmonic_sum(self, plane, n_harm: int, out=None, n_r: int | None = None, stream=None):
         """Enqueue ``jerk_harmonic_sum`` over a full (T, >= n_r) float32 plane; returns ``out``
         ((n_zf * n_wf, >= n_pf) float32, allocated here when omitted)."""

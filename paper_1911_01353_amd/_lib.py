@@ -142,6 +142,11 @@ SIGNATURES = {
                                      C.c_size_t, C.c_void_p]),
     "jerk_find_candidates": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_void_p, C.c_double,
                                          C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "jerk_search_candidates_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_double,
+                                                            C.c_int64]),
+    "jerk_search_candidates": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                           C.c_double, C.c_double, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
+                                           C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "jerk_serve_create": (C.c_int32, [C.POINTER(ServeDesc), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
     "jerk_serve_submit": (C.c_int32, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
     "jerk_serve_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(Result)]),

@@ -14,6 +14,9 @@
 // and not less than its right one (row ends have no neighbour on that side).
 // Hits are staged in LDS per workgroup and appended with one atomic add on the
 // shared counter per flush.
+#include <algorithm>
+
+#include "cand_device.h"
 #include "jerk_internal.h"
 
 namespace jerk {
@@ -257,7 +260,261 @@ int32_t stat_chunks(int32_t rows, int64_t n_r) {
   return (int32_t)(c < 1 ? 1 : c);
 }
 
+// ---- steps of the fused search with candidate selection --------------------
+// (the FFT passes are in fft_correlate.hip). Rows are members of one width
+// group; the per-(row, segment) partial sums cover 2 lim points, lim =
+// min(U, nbins - s U) lags of segment s.
+
+__global__ void __launch_bounds__(256) cand_reset_kernel(int32_t* __restrict__ ovf, int32_t rows,
+                                                         uint32_t* __restrict__ n_flagged,
+                                                         unsigned long long* __restrict__ pool_count) {
+  for (int32_t i = blockIdx.x * 256 + threadIdx.x; i < rows; i += gridDim.x * 256) ovf[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *n_flagged = 0u;
+    *pool_count = 0ull;
+  }
+}
+
+// One wave per row: lane l merges a contiguous run of the row's segments, then
+// the lanes are merged in index order. A row is flagged for the exact pass when
+// its threshold lies below the speculative level or when one of its staged hits
+// found no room (tile slots and pool full).
+__global__ void __launch_bounds__(256) cand_finish_kernel(const double2* __restrict__ part, int32_t rows,
+                                                          int64_t n_seg, int32_t U, int64_t nbins,
+                                                          const int32_t* __restrict__ ovf, double k_sigma, double pre,
+                                                          const int32_t* __restrict__ members, int32_t t_begin,
+                                                          double* __restrict__ stats_out, CandRowStat* __restrict__ rs,
+                                                          int32_t* __restrict__ flagged, uint32_t* __restrict__ n_flagged) {
+  const int lane = threadIdx.x & 63;
+  const int32_t row = (int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6);
+  if (row >= rows) return;  // whole waves
+  const int64_t run = (n_seg + 63) / 64;
+  const int64_t s0 = lane * run;
+  const int64_t s1 = s0 + run < n_seg ? s0 + run : n_seg;
+  Moments acc{0.0, 0.0, 0.0};
+  for (int64_t sg = s0; sg < s1; ++sg) {
+    const double2 v = part[(int64_t)row * n_seg + sg];
+    const int64_t lim = nbins - sg * U < U ? nbins - sg * U : U;
+    Moments g;
+    g.n = 2.0 * (double)lim;
+    g.m = v.x / g.n;
+    g.m2 = fmax(0.0, v.y - v.x * g.m);
+    acc = merge(acc, g);
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const Moments o = shfl_xor_moments(acc, off);
+    acc = (lane & off) ? merge(o, acc) : merge(acc, o);
+  }
+  if (lane == 0) {
+    CandRowStat st;
+    st.mean = acc.m;
+    st.sigma = acc.n > 0.0 ? sqrt(acc.m2 / acc.n) : 0.0;
+    st.thr = st.mean + k_sigma * st.sigma;
+    st.flag = (ovf[row] != 0 || st.thr < pre) ? 1 : 0;
+    st.pad = 0;
+    rs[row] = st;
+    if (stats_out) {
+      const int64_t o = 2 * (int64_t)(members[row] - t_begin);
+      stats_out[o] = st.mean;
+      stats_out[o + 1] = st.sigma;
+    }
+    if (st.flag) flagged[atomicAdd(n_flagged, 1u)] = row;
+  }
+}
+
+// Staged hits of rows that are not flagged and lie above their row's threshold:
+// first the tiles' slots, a thread per tile looping over its hits (the loop bound
+// is the block's largest count, so every thread reaches the barriers), then the
+// pool. Kept candidates are gathered in LDS and appended with one atomic add on
+// the shared counter per flush: a step adds at most 256, so the stage is flushed
+// once fewer than 256 of its slots are free.
+constexpr int kFilterStage = 2048;
+
+__global__ void __launch_bounds__(256) cand_filter_kernel(const CandHit* __restrict__ hits,
+                                                          const uint32_t* __restrict__ tile_hits, int32_t tiles,
+                                                          int32_t cap_tile, int32_t n_seg, int32_t tpb, int32_t U,
+                                                          const CandPoolHit* __restrict__ pool,
+                                                          const unsigned long long* __restrict__ pool_count,
+                                                          int64_t pool_cap, const CandRowStat* __restrict__ rs,
+                                                          const int32_t* __restrict__ members,
+                                                          jerk_candidate* __restrict__ out, int64_t capacity,
+                                                          unsigned long long* __restrict__ count) {
+  __shared__ jerk_candidate stage[kFilterStage];
+  __shared__ int n_stage;
+  __shared__ unsigned long long s_base;
+  __shared__ int32_t s_most[4];
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (1ull << lane) - 1ull;
+  if (threadIdx.x == 0) n_stage = 0;
+  __syncthreads();
+  // Entered by all threads together; reads of n_stage that decide a branch sit between barriers.
+  auto flush = [&]() {
+    __syncthreads();
+    const int n = n_stage;
+    __syncthreads();
+    if (n == 0) return;
+    if (threadIdx.x == 0) s_base = atomicAdd(count, (unsigned long long)n);
+    __syncthreads();
+    const unsigned long long b = s_base;
+    for (int i = threadIdx.x; i < n; i += 256)
+      if (b + (unsigned long long)i < (unsigned long long)capacity) out[b + i] = stage[i];
+    __syncthreads();
+    if (threadIdx.x == 0) n_stage = 0;
+    __syncthreads();
+  };
+  auto push = [&](bool keep, const jerk_candidate& c) {
+    const uint64_t mask = __ballot(keep);
+    if (mask == 0ull) return;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    int slot = 0;
+    if (lane == leader) slot = atomicAdd(&n_stage, __popcll(mask));
+    slot = __builtin_amdgcn_readlane(slot, leader);
+    if (keep) stage[slot + __popcll(mask & below)] = c;
+  };
+  auto step_done = [&]() {
+    __syncthreads();
+    const bool full = n_stage > kFilterStage - 256;
+    __syncthreads();
+    if (full) flush();
+  };
+  for (int32_t base = blockIdx.x * 256; base < tiles; base += gridDim.x * 256) {
+    const int32_t tile = base + (int32_t)threadIdx.x;
+    int32_t cnt = 0, row0 = 0;
+    uint32_t p0 = 0u;
+    if (tile < tiles) {
+      const uint32_t c = tile_hits[tile];
+      cnt = c < (uint32_t)cap_tile ? (int32_t)c : cap_tile;
+      row0 = (tile / n_seg) * tpb;
+      p0 = 2u * (uint32_t)(tile % n_seg) * (uint32_t)U;
+    }
+    int32_t most = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t o = __shfl_xor(most, off, 64);
+      most = o > most ? o : most;
+    }
+    if (lane == 0) s_most[threadIdx.x >> 6] = most;
+    __syncthreads();
+    most = max(max(s_most[0], s_most[1]), max(s_most[2], s_most[3]));
+    __syncthreads();
+    for (int32_t k = 0; k < most; ++k) {
+      bool keep = false;
+      jerk_candidate cd{0u, 0u, 0.0f, 0.0f};
+      if (k < cnt) {
+        const CandHit h = hits[(int64_t)tile * cap_tile + k];
+        const int32_t row = row0 + (int32_t)(h.code >> 16);
+        const CandRowStat st = rs[row];
+        keep = !st.flag && (double)h.power > st.thr;
+        if (keep) {
+          cd.t = (uint32_t)members[row];
+          cd.p = p0 + (h.code & 0xFFFFu);
+          cd.power = h.power;
+          cd.sigma = (float)(((double)h.power - st.mean) / st.sigma);
+        }
+      }
+      push(keep, cd);
+      step_done();
+    }
+  }
+  const unsigned long long pc = *pool_count;
+  const int64_t np = pc < (unsigned long long)pool_cap ? (int64_t)pc : pool_cap;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < np; base += (int64_t)gridDim.x * 256) {
+    const int64_t i = base + threadIdx.x;
+    bool keep = false;
+    jerk_candidate cd{0u, 0u, 0.0f, 0.0f};
+    if (i < np) {
+      const CandPoolHit h = pool[i];
+      const CandRowStat st = rs[h.row];
+      keep = !st.flag && (double)h.power > st.thr;
+      if (keep) {
+        cd.t = (uint32_t)members[h.row];
+        cd.p = h.p;
+        cd.power = h.power;
+        cd.sigma = (float)(((double)h.power - st.mean) / st.sigma);
+      }
+    }
+    push(keep, cd);
+    step_done();
+  }
+  flush();
+}
+
+// The first and last point of every (row, segment), whose neighbours lie in the
+// adjacent segments. edge[2 i] = (P0, P1) at lag 0, edge[2 i + 1] = (P0, P1) at
+// the last lag, i = row n_seg + segment.
+__global__ void __launch_bounds__(256) cand_edges_kernel(const float2* __restrict__ edge, int32_t rows, int64_t n_seg,
+                                                         int32_t U, int64_t nbins, const CandRowStat* __restrict__ rs,
+                                                         const int32_t* __restrict__ members,
+                                                         jerk_candidate* __restrict__ out, int64_t capacity,
+                                                         unsigned long long* __restrict__ count) {
+  const int64_t total = (int64_t)rows * n_seg;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < total; base += (int64_t)gridDim.x * 256) {
+    const int64_t i = base + threadIdx.x;
+    bool h0 = false, h1 = false;
+    float a0 = 0.0f, b1 = 0.0f;
+    uint32_t t = 0u, p0 = 0u, p1 = 0u;
+    CandRowStat st{0.0, 0.0, 0.0, 0, 0};
+    if (i < total) {
+      const int32_t r = (int32_t)(i / n_seg);
+      const int64_t sg = i % n_seg;
+      const float2 first = edge[2 * i], last = edge[2 * i + 1];
+      st = rs[r];
+      t = (uint32_t)members[r];
+      const int64_t lim = nbins - sg * U < U ? nbins - sg * U : U;
+      a0 = first.x;
+      b1 = last.y;
+      p0 = (uint32_t)(2 * (sg * U));
+      p1 = (uint32_t)(2 * (sg * U + lim - 1) + 1);
+      const bool left_ok = sg == 0 || a0 > edge[2 * (i - 1) + 1].y;
+      h0 = left_ok && a0 >= first.y && (double)a0 > st.thr;
+      const bool right_ok = sg + 1 == n_seg || b1 >= edge[2 * (i + 1)].x;
+      h1 = b1 > last.x && right_ok && (double)b1 > st.thr;
+    }
+    emit_candidates(h0, t, p0, a0, st.mean, st.sigma, out, capacity, count);
+    emit_candidates(h1, t, p1, b1, st.mean, st.sigma, out, capacity, count);
+  }
+}
+
 }  // namespace
+
+void cand_reset(int32_t* ovf, int32_t rows, uint32_t* n_flagged, unsigned long long* pool_count, hipStream_t stream) {
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(1024, ((int64_t)rows + 255) / 256));
+  hipLaunchKernelGGL(cand_reset_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, ovf, rows, n_flagged,
+                     pool_count);
+  JERK_HIP_CHECK(hipGetLastError());
+}
+
+void cand_finish(const double2* part, int32_t rows, int64_t n_seg, int32_t U, int64_t nbins, const int32_t* ovf,
+                 double k_sigma, double pre, const int32_t* d_members, int32_t t_begin, double* stats_out,
+                 CandRowStat* rs, int32_t* flagged, uint32_t* n_flagged, hipStream_t stream) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(cand_finish_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, part, rows, n_seg,
+                     U, nbins, ovf, k_sigma, pre, d_members, t_begin, stats_out, rs, flagged, n_flagged);
+  JERK_HIP_CHECK(hipGetLastError());
+}
+
+void cand_filter(const CandHit* hits, const uint32_t* tile_hits, int32_t tiles, int32_t cap_tile, int32_t n_seg,
+                 int32_t tpb, int32_t U, const CandPoolHit* pool, const unsigned long long* pool_count,
+                 int64_t pool_cap, const CandRowStat* rs, const int32_t* d_members, jerk_candidate* out,
+                 int64_t capacity, unsigned long long* count, hipStream_t stream) {
+  if (tiles <= 0) return;
+  const int64_t blocks = std::min<int64_t>(4096, ((int64_t)tiles + 255) / 256);
+  hipLaunchKernelGGL(cand_filter_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, hits, tile_hits, tiles,
+                     cap_tile, n_seg, tpb, U, pool, pool_count, pool_cap, rs, d_members, out, capacity, count);
+  JERK_HIP_CHECK(hipGetLastError());
+}
+
+void cand_edges(const float2* edge, int32_t rows, int64_t n_seg, int32_t U, int64_t nbins, const CandRowStat* rs,
+                const int32_t* d_members, jerk_candidate* out, int64_t capacity, unsigned long long* count,
+                hipStream_t stream) {
+  const int64_t total = (int64_t)rows * n_seg;
+  if (total <= 0) return;
+  const int64_t blocks = std::min<int64_t>(4096, (total + 255) / 256);
+  hipLaunchKernelGGL(cand_edges_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, edge, rows, n_seg, U, nbins,
+                     rs, d_members, out, capacity, count);
+  JERK_HIP_CHECK(hipGetLastError());
+}
 
 size_t stats_workspace_bytes(int32_t rows, int64_t n_r) {
   return (size_t)(rows > 0 ? rows : 0) * (size_t)stat_chunks(rows, n_r) * sizeof(Moments);

@@ -436,6 +436,32 @@ int32_t jerk_find_candidates(const float* d_plane, int64_t ld, int32_t rows, int
   });
 }
 
+size_t jerk_search_candidates_workspace_bytes(const jerk_plan* plan, int64_t nbins, int32_t t_begin, int32_t t_end,
+                                              double pre_level, int64_t staged) {
+  if (!plan || nbins < 1 || nbins >= (int64_t(1) << 31) || staged < 0 || !std::isfinite(pre_level) || t_begin < 0 ||
+      t_end < t_begin || t_end > plan->p.T)
+    return 0;
+  return jerk::search_candidates_workspace_bytes(plan->p, nbins, t_begin, t_end, pre_level, staged);
+}
+
+int32_t jerk_search_candidates(const jerk_plan* plan, const void* d_bank, const void* d_spec, int64_t nbins,
+                               int32_t t_begin, int32_t t_end, double k_sigma, double pre_level, int64_t staged,
+                               double* d_stats, jerk_candidate* d_out, int64_t capacity,
+                               unsigned long long* d_count, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    require(plan != nullptr, JERK_EINVAL, "plan must not be NULL");
+    require(t_begin >= 0 && t_begin <= t_end && t_end <= plan->p.T, JERK_EINVAL, "bad template range");
+    require(nbins >= 1 && nbins < (int64_t(1) << 31), JERK_EINVAL, "nbins must be in [1, 2^31)");
+    require(std::isfinite(k_sigma) && std::isfinite(pre_level), JERK_EINVAL, "k_sigma and pre_level must be finite");
+    require(staged >= 0 && capacity >= 0, JERK_EINVAL, "staged and capacity must be >= 0");
+    if (t_begin == t_end) return;
+    require(d_bank && d_spec && d_count && d_ws, JERK_EINVAL, "bank, spectrum, count and workspace must not be NULL");
+    require(d_out || capacity == 0, JERK_EINVAL, "output must not be NULL when capacity > 0");
+    jerk::search_candidates(plan->p, d_bank, d_spec, nbins, t_begin, t_end, k_sigma, pre_level, d_stats, d_out,
+                            capacity, d_count, staged, d_ws, ws_bytes, stream);
+  });
+}
+
 size_t jerk_autotune_scratch_bytes(const jerk_plan* plan, int64_t nbins) {
   if (!plan || nbins < 1) return 0;
   return jerk::autotune_scratch_bytes(plan->p, nbins);

@@ -20,6 +20,7 @@
 // templates; the forward FFT of the segment is done once per workgroup.
 #include <algorithm>
 
+#include "cand_device.h"
 #include "jerk_internal.h"
 
 namespace jerk {
@@ -171,13 +172,216 @@ __device__ __forceinline__ uint64_t peak_key(float power, int64_t p) {
   return ((uint64_t)__float_as_uint(power) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)p);
 }
 
-// One tile: segment `seg` of job `j` against template block `tb` (up to j.tpb
-// templates of the job's member range). Writes the plane rows and/or the
-// per-(row, segment) peak keys. Radices R1..R4 (R4 = 1: three passes) run
-// forward in that order and inverse in the reverse order.
-template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS>
-__device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int tb, float2* lds, uint64_t* red,
-                                         const float2* __restrict__ tw) {
+// Candidate epilogue of one template row of a tile (paper, section "Results":
+// statistics of the plane and a peak finder with a user threshold, here without
+// writing the plane). P0[e] and P1[e] are the powers at plane points
+// p = 2 (seg U + lag) + phase of lag = tid + TPB c, the register of column c
+// being e = (c mod M) R1 + c / M (M = E / R1). A point is a peak when it is
+// strictly above its left neighbour and not below its right one. The left
+// neighbour of phase 0 at a lag is phase 1 at the lag before, the right one of
+// phase 1 is phase 0 at the next lag: one lane over, across a wave boundary from
+// the neighbouring wave, and across a column boundary from the last (first)
+// thread of the previous (next) column. The segment's first point (phase 0 at
+// lag 0) and last point (phase 1 at its last lag) have a neighbour in another
+// segment and are decided later from the stored edge powers.
+//   Mode 1 (speculative): writes the row's sum and sum of squares over the
+//   segment (FP64, fixed order), the edge powers, and stages the interior peaks
+//   above ca.pre in the tile's own run of ca.cap_tile slots (counted in LDS, so
+//   no device-wide atomics, and none at all when the workgroup is one wave);
+//   hits past the run go to the shared pool (one atomic per wave and template),
+//   and a hit that finds the pool full marks its row in ca.ovf.
+// The wave takes its peaks of all columns first and reserves their slots once.
+//   Mode 2 (exact): appends the interior peaks above the row's final threshold
+//   to the candidate list.
+template <int S, int E, int R1, int CAND>
+__device__ __forceinline__ void cand_epilogue(const CandArgs& ca, const FftJob& j, int64_t seg, int U, int lag_lim,
+                                              int64_t row, int64_t row0, int t, const float (&P0)[E],
+                                              const float (&P1)[E], float* xch, double2* wsum, uint32_t* n_hit,
+                                              int tid) {
+  constexpr int TPB = S / E;
+  constexpr int M = E / R1;
+  constexpr int W = TPB / 64;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t slot = row * j.n_seg + seg;
+  double s = 0.0, q = 0.0;
+  if constexpr (CAND == 1) {
+#pragma unroll
+    for (int c = 0; c < E; ++c) {
+      const int e = (c % M) * R1 + c / M;
+      if (tid + TPB * c < lag_lim) {
+        const double a = (double)P0[e], b = (double)P1[e];
+        s += a;
+        s += b;
+        q = fma(a, a, q);
+        q = fma(b, b, q);
+      }
+    }
+    s = wave_sum_f64(s);
+    q = wave_sum_f64(q);
+  }
+  // fl[c]: P1 one lag left of lane 0's lag in column c; fr[c]: P0 one lag right of lane 63's.
+  float fl[E], fr[E];
+  if constexpr (W == 1) {
+#pragma unroll
+    for (int c = 0; c < E; ++c) {
+      fl[c] = c > 0 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(P1[((c - 1) % M) * R1 + (c - 1) / M]), 63))
+                    : 0.0f;
+      fr[c] = c + 1 < E
+                  ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(P0[((c + 1) % M) * R1 + (c + 1) / M]), 0))
+                  : 0.0f;
+    }
+  } else {
+    float* xl = xch;          // [W][E]: P1 of lane 63 of each wave
+    float* xr = xch + W * E;  // [W][E]: P0 of lane 0 of each wave
+    if (lane == 63) {
+#pragma unroll
+      for (int c = 0; c < E; ++c) xl[wave * E + c] = P1[(c % M) * R1 + c / M];
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < E; ++c) xr[wave * E + c] = P0[(c % M) * R1 + c / M];
+      if constexpr (CAND == 1) wsum[wave] = make_double2(s, q);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < E; ++c) {
+      fl[c] = wave > 0 ? xl[(wave - 1) * E + c] : (c > 0 ? xl[(W - 1) * E + c - 1] : 0.0f);
+      fr[c] = wave + 1 < W ? xr[(wave + 1) * E + c] : (c + 1 < E ? xr[c + 1] : 0.0f);
+    }
+    if constexpr (CAND == 1) {
+      if (tid == 0) {
+        s = wsum[0].x;
+        q = wsum[0].y;
+#pragma unroll
+        for (int w = 1; w < W; ++w) {
+          s += wsum[w].x;
+          q += wsum[w].y;
+        }
+      }
+    }
+  }
+  double thr, mean = 0.0, sigma = 0.0;
+  if constexpr (CAND == 1) {
+    thr = ca.pre;
+    if (tid == 0) {
+      ca.part[slot] = make_double2(s, q);
+      ca.edge[2 * slot] = make_float2(P0[0], P1[0]);
+    }
+    const int last = lag_lim - 1;
+    if (tid == last % TPB) {
+      const int cl = last / TPB;
+#pragma unroll
+      for (int c = 0; c < E; ++c) {
+        const int e = (c % M) * R1 + c / M;
+        if (c == cl) ca.edge[2 * slot + 1] = make_float2(P0[e], P1[e]);
+      }
+    }
+  } else {
+    const CandRowStat st = ca.rs[row];
+    thr = st.thr;
+    mean = st.mean;
+    sigma = st.sigma;
+  }
+  // For a float x, (double) x > thr exactly when x > thr rounded down to a float.
+  const float thr_f = __double2float_rd(thr);
+  const int64_t pbase = 2 * (seg * U);
+  uint64_t hm[E], h1m[E];  // per column: lanes with a peak, lanes whose peak is the phase-1 point
+  uint32_t total = 0;
+#pragma unroll
+  for (int c = 0; c < E; ++c) {
+    const int e = (c % M) * R1 + c / M;
+    const float a = P0[e], b = P1[e];
+    const float left = dpp_f32<0x138>(fl[c], b);   // lane i reads P1 of lane i - 1
+    const float right = dpp_f32<0x130>(fr[c], a);  // lane i reads P0 of lane i + 1
+    const int lag = tid + TPB * c;
+    const bool h0 = lag > 0 && lag < lag_lim && a > left && a >= b && a > thr_f;
+    const bool h1 = lag + 1 < lag_lim && b > a && b >= right && b > thr_f;
+    hm[c] = __ballot(h0 || h1);  // never both: h0 needs a >= b, h1 needs b > a
+    h1m[c] = __ballot(h1);
+    total += (uint32_t)__popcll(hm[c]);
+  }
+  if (total == 0u) return;  // wave-uniform
+  const uint64_t below = (1ull << lane) - 1ull;
+  // one reservation for all the wave's peaks of this template
+  if constexpr (CAND == 1) {
+    uint32_t base;
+    if constexpr (W == 1) {
+      base = *n_hit;  // the workgroup is this wave: the running count is a register
+      *n_hit = base + total;
+    } else {
+      uint32_t b0 = 0;
+      if (lane == 0) b0 = atomicAdd(n_hit, total);
+      base = (uint32_t)__builtin_amdgcn_readlane((int)b0, 0);
+    }
+    const uint32_t cap = (uint32_t)ca.cap_tile;
+    const uint32_t first = base > cap ? base : cap;  // slot index of the first hit beyond the tile's run
+    unsigned long long pb = 0;
+    if (base + total > cap) {  // wave-uniform: the excess goes to the pool
+      unsigned long long p0 = 0;
+      if (lane == 0) p0 = atomicAdd(ca.pool_count, (unsigned long long)(base + total - first));
+      const int lo = __builtin_amdgcn_readlane((int)(unsigned)(p0 & 0xffffffffull), 0);
+      const int hi = __builtin_amdgcn_readlane((int)(p0 >> 32), 0);
+      pb = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+    }
+    uint32_t run = base;
+#pragma unroll
+    for (int c = 0; c < E; ++c) {
+      if (hm[c] == 0ull) continue;  // wave-uniform
+      if ((hm[c] >> lane) & 1ull) {
+        const int e = (c % M) * R1 + c / M;
+        const bool h1 = (h1m[c] >> lane) & 1ull;
+        const uint32_t poff = (uint32_t)(2 * (tid + TPB * c) + (h1 ? 1 : 0));
+        const float pw = h1 ? P1[e] : P0[e];
+        const uint32_t i = run + (uint32_t)__popcll(hm[c] & below);
+        if (i < cap) {
+          ca.hits[(int64_t)blockIdx.x * cap + i] = CandHit{((uint32_t)(row - row0) << 16) | poff, pw};
+        } else {
+          const unsigned long long q = pb + (i - first);
+          if (q < (unsigned long long)ca.pool_cap)
+            ca.pool[q] = CandPoolHit{(uint32_t)row, (uint32_t)pbase + poff, pw, 0u};
+          else
+            ca.ovf[row] = 1;
+        }
+      }
+      run += (uint32_t)__popcll(hm[c]);
+    }
+  } else {
+    unsigned long long g0 = 0;
+    if (lane == 0) g0 = atomicAdd(ca.count, (unsigned long long)total);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)(g0 & 0xffffffffull), 0);
+    const int hi = __builtin_amdgcn_readlane((int)(g0 >> 32), 0);
+    unsigned long long run = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+#pragma unroll
+    for (int c = 0; c < E; ++c) {
+      if (hm[c] == 0ull) continue;  // wave-uniform
+      if ((hm[c] >> lane) & 1ull) {
+        const int e = (c % M) * R1 + c / M;
+        const bool h1 = (h1m[c] >> lane) & 1ull;
+        const unsigned long long i = run + (unsigned long long)__popcll(hm[c] & below);
+        if (i < (unsigned long long)ca.capacity) {
+          jerk_candidate cd;
+          cd.t = (uint32_t)t;
+          cd.p = (uint32_t)pbase + (uint32_t)(2 * (tid + TPB * c) + (h1 ? 1 : 0));
+          cd.power = h1 ? P1[e] : P0[e];
+          cd.sigma = (float)(((double)cd.power - mean) / sigma);
+          ca.out[i] = cd;
+        }
+      }
+      run += (unsigned long long)__popcll(hm[c]);
+    }
+  }
+}
+
+// One tile: segment `seg` of job `j` against members [m0, m1) of its member
+// list. CAND = 0 writes the plane rows and/or the per-(row, segment) peak
+// keys; CAND = 1 and 2 write neither and run the candidate epilogue instead
+// (cand_epilogue). Radices R1..R4 (R4 = 1: three passes) run forward in that
+// order and inverse in the reverse order.
+template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS, int CAND = 0>
+__device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, int m1, float2* lds, uint64_t* red,
+                                         const float2* __restrict__ tw, const CandArgs* ca = nullptr,
+                                         float* xch = nullptr, double2* wsum = nullptr, uint32_t* n_hit = nullptr) {
   constexpr int TPB = S / E;
   constexpr bool P4 = R4 > 1;
   constexpr int RL = P4 ? R4 : R3;  // last forward radix = first inverse radix
@@ -213,8 +417,6 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int tb, f
   for (int e = 0; e < E; ++e) F[e] = v[e];
 
   // ---- template loop ----
-  const int m0 = j.m_begin + tb * j.tpb;
-  const int m1 = min(m0 + j.tpb, j.m_end);
   // lags kept by this segment: lag < U and k0 = seg U + lag < nbins
   const int lag_lim = (int)min((int64_t)U, j.nbins - seg * U);
   for (int mm = m0; mm < m1; ++mm) {
@@ -247,6 +449,12 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int tb, f
       if (phase == 0) {
 #pragma unroll
         for (int e = 0; e < E; ++e) P0[e] = fmaf(v[e].x, v[e].x, v[e].y * v[e].y);
+      } else if constexpr (CAND > 0) {
+        float P1[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) P1[e] = fmaf(v[e].x, v[e].x, v[e].y * v[e].y);
+        cand_epilogue<S, E, R1, CAND>(*ca, j, seg, U, lag_lim, row, (int64_t)(m0 - j.row_base), t, P0, P1, xch,
+                                      wsum, n_hit, tid);
       } else {
         constexpr int M = E / R1;
         [[maybe_unused]] uint64_t best = 0;
@@ -293,7 +501,8 @@ __global__ void __launch_bounds__(S / E) fft_correlate_kernel(FftJob j, const fl
   __shared__ float2 lds[S + S / 16];
   __shared__ uint64_t red[8];
   const int64_t blk = blockIdx.x;
-  fft_tile<S, E, R1, R2, R3, R4, KEYS>(j, blk % j.n_seg, (int)(blk / j.n_seg), lds, red, tw);
+  const int m0 = j.m_begin + (int)(blk / j.n_seg) * j.tpb;
+  fft_tile<S, E, R1, R2, R3, R4, KEYS>(j, blk % j.n_seg, m0, min(m0 + j.tpb, j.m_end), lds, red, tw);
 }
 
 // Persistent launch over a job table: every workgroup takes tiles from a
@@ -328,7 +537,8 @@ __global__ void __launch_bounds__(S / E) fft_persistent_kernel(const FftJob* __r
     // tiles, which costs more registers (and waves) than reloading them.
     const float2* twt = tw;
     asm volatile("" : "+s"(twt));
-    fft_tile<S, E, R1, R2, R3, R4, KEYS>(j, local % j.n_seg, (int)(local / j.n_seg), lds, red, twt);
+    const int m0 = j.m_begin + (int)(local / j.n_seg) * j.tpb;
+    fft_tile<S, E, R1, R2, R3, R4, KEYS>(j, local % j.n_seg, m0, min(m0 + j.tpb, j.m_end), lds, red, twt);
   }
 }
 
@@ -350,7 +560,42 @@ __global__ void __launch_bounds__(S / E) fft_multi_kernel(const FftJob* __restri
   }
   const FftJob& j = jobs[lo];
   const int64_t local = tile - j.tile_begin;
-  fft_tile<S, E, R1, R2, R3, R4, KEYS>(j, local % j.n_seg, (int)(local / j.n_seg), lds, red, tw);
+  const int m0 = j.m_begin + (int)(local / j.n_seg) * j.tpb;
+  fft_tile<S, E, R1, R2, R3, R4, KEYS>(j, local % j.n_seg, m0, min(m0 + j.tpb, j.m_end), lds, red, tw);
+}
+
+// Candidate passes over one width-group job (cand_epilogue). Mode 1: one
+// workgroup per tile (template block, segment), as fft_correlate_kernel. Mode 2:
+// the flagged rows, one template per tile, the grid striding over (flagged row,
+// segment) tiles; with no flagged row every workgroup exits at once.
+template <int S, int E, int R1, int R2, int R3, int R4, int CAND>
+__global__ void __launch_bounds__(S / E) fft_cand_kernel(FftJob j, const float2* __restrict__ tw, CandArgs ca) {
+  constexpr int W = S / E / 64;
+  __shared__ float2 lds[S + S / 16];
+  __shared__ uint64_t red[8];
+  __shared__ float xch[2 * W * E];
+  __shared__ double2 wsum[W];
+  __shared__ uint32_t n_hit_lds;  // hits of the tile, counted by every wave (W > 1)
+  if constexpr (CAND == 1) {
+    uint32_t n_hit_reg = 0u;  // hits of the tile when the workgroup is one wave
+    if (threadIdx.x == 0) n_hit_lds = 0u;  // the forward transform's barriers order this before any use
+    const int64_t blk = blockIdx.x;
+    const int m0 = j.m_begin + (int)(blk / j.n_seg) * j.tpb;
+    fft_tile<S, E, R1, R2, R3, R4, false, 1>(j, blk % j.n_seg, m0, min(m0 + j.tpb, j.m_end), lds, red, tw, &ca, xch,
+                                             wsum, W == 1 ? &n_hit_reg : &n_hit_lds);
+    if constexpr (W == 1) {
+      if (threadIdx.x == 0) ca.tile_hits[blk] = n_hit_reg;
+    } else {
+      __syncthreads();
+      if (threadIdx.x == 0) ca.tile_hits[blk] = n_hit_lds;
+    }
+  } else {
+    const int64_t tiles = (int64_t)*ca.n_flagged * j.n_seg;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+      const int m0 = j.m_begin + ca.flagged[tile / j.n_seg];
+      fft_tile<S, E, R1, R2, R3, R4, false, 2>(j, tile % j.n_seg, m0, m0 + 1, lds, red, tw, &ca, xch, wsum);
+    }
+  }
 }
 
 __global__ void batch_reset_kernel(BatchHeader* hdr) {
@@ -402,6 +647,39 @@ void fft_correlate_launch(FftJob j, int32_t seg_len, int32_t ept, const float2* 
                          stream, j, twiddles);                                                                    \
     JERK_HIP_CHECK(hipGetLastError());                                                                            \
     return;                                                                                                       \
+  }
+  JERK_FFT_VARIANTS(X)
+#undef X
+  throw Error(JERK_EINTERNAL, "unsupported FFT kernel variant");
+}
+
+void fft_cand_launch(FftJob j, int32_t seg_len, int32_t ept, const float2* twiddles, const CandArgs& ca, int mode,
+                     hipStream_t stream) {
+  if (j.m_end <= j.m_begin || j.nbins <= 0) return;
+  require(j.plane == nullptr && j.row_max == nullptr && j.row_by_member && j.row_base == j.m_begin, JERK_EINTERNAL,
+          "candidate passes take a group job without plane or keys");
+  const int64_t tiles = fft_job_tiles(j, seg_len);
+  require(tiles < (1ll << 31), JERK_EINVAL, "search too large for one launch; split the template range");
+  int dev = 0, cus = 0, per_cu = 0;
+  if (mode == 2) {
+    JERK_HIP_CHECK(hipGetDevice(&dev));
+    JERK_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  const int64_t row_tiles = (int64_t)(j.m_end - j.m_begin) * j.n_seg;
+#define X(S, E, A, B, C, D)                                                                                      \
+  if (seg_len == S && ept == E) {                                                                                \
+    if (mode == 1) {                                                                                             \
+      hipLaunchKernelGGL((fft_cand_kernel<S, E, A, B, C, D, 1>), dim3((unsigned)tiles), dim3(S / E), 0, stream, j, \
+                         twiddles, ca);                                                                          \
+    } else {                                                                                                     \
+      JERK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(                                               \
+          &per_cu, reinterpret_cast<const void*>(fft_cand_kernel<S, E, A, B, C, D, 2>), S / E, 0));              \
+      const int64_t grid = std::min<int64_t>(row_tiles, (int64_t)std::max(1, cus) * std::max(1, per_cu));       \
+      hipLaunchKernelGGL((fft_cand_kernel<S, E, A, B, C, D, 2>), dim3((unsigned)grid), dim3(S / E), 0, stream, j, \
+                         twiddles, ca);                                                                          \
+    }                                                                                                            \
+    JERK_HIP_CHECK(hipGetLastError());                                                                           \
+    return;                                                                                                      \
   }
   JERK_FFT_VARIANTS(X)
 #undef X

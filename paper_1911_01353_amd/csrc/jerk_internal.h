@@ -115,6 +115,66 @@ struct BatchHeader {
   int32_t n_jobs;
   int32_t pad;
 };
+// Candidate selection fused into the FFT path (search_candidates.cpp). Rows are the
+// members [lo, hi) of one width group's member list, row r = member lo + r.
+struct CandRowStat {
+  double mean, sigma, thr;  // thr = mean + k sigma
+  int32_t flag;             // the row is recomputed by the exact pass
+  int32_t pad;
+};
+struct CandHit {   // a staged hit of the speculative pass, in its tile's run of slots
+  uint32_t code;   // (row - first row of the tile's template block) << 16 | (p - 2 seg U)
+  float power;
+};
+struct CandPoolHit {  // a staged hit beyond its tile's slots
+  uint32_t row, p;
+  float power;
+  uint32_t pad;
+};
+struct CandArgs {
+  // speculative pass (mode 1); tile i = template block * n_seg + segment
+  double pre;                     // interior peaks above this level are staged
+  double2* part;                  // [rows][n_seg] (sum, sum of squares) of the row's powers in the segment
+  float2* edge;                   // [rows][n_seg][2] (P0, P1) at lag 0 and at the segment's last lag
+  CandHit* hits;                  // [tiles][cap_tile]
+  uint32_t* tile_hits;            // [tiles] hits found (also those beyond cap_tile)
+  CandPoolHit* pool;              // hits beyond their tile's slots, pool_count of them (shared, atomic)
+  unsigned long long* pool_count;
+  int64_t pool_cap;
+  int32_t* ovf;                   // [rows] set when a hit of the row found no room in the pool either
+  int32_t cap_tile;
+  // exact pass (mode 2) and the final list
+  const CandRowStat* rs;          // [rows]
+  const int32_t* flagged;         // rows to recompute, n_flagged of them
+  const uint32_t* n_flagged;
+  jerk_candidate* out;
+  int64_t capacity;
+  unsigned long long* count;
+};
+// Speculative pass (mode 1) over a group job (plane and row_max null, row_by_member set,
+// row_base = m_begin); exact pass (mode 2) over the flagged rows of the same job.
+void fft_cand_launch(FftJob j, int32_t seg_len, int32_t ept, const float2* twiddles, const CandArgs& ca, int mode,
+                     hipStream_t stream);
+// candidates.hip: the steps between and after the FFT passes.
+void cand_reset(int32_t* ovf, int32_t rows, uint32_t* n_flagged, unsigned long long* pool_count, hipStream_t stream);
+void cand_finish(const double2* part, int32_t rows, int64_t n_seg, int32_t U, int64_t nbins, const int32_t* ovf,
+                 double k_sigma, double pre, const int32_t* d_members, int32_t t_begin, double* stats_out,
+                 CandRowStat* rs, int32_t* flagged, uint32_t* n_flagged, hipStream_t stream);
+void cand_filter(const CandHit* hits, const uint32_t* tile_hits, int32_t tiles, int32_t cap_tile, int32_t n_seg,
+                 int32_t tpb, int32_t U, const CandPoolHit* pool, const unsigned long long* pool_count,
+                 int64_t pool_cap, const CandRowStat* rs, const int32_t* d_members, jerk_candidate* out,
+                 int64_t capacity, unsigned long long* count, hipStream_t stream);
+void cand_edges(const float2* edge, int32_t rows, int64_t n_seg, int32_t U, int64_t nbins, const CandRowStat* rs,
+                const int32_t* d_members, jerk_candidate* out, int64_t capacity, unsigned long long* count,
+                hipStream_t stream);
+// search_candidates.cpp
+size_t search_candidates_workspace_bytes(const Plan& p, int64_t nbins, int32_t t_begin, int32_t t_end, double pre,
+                                         int64_t staged);
+void search_candidates(const Plan& p, const void* d_bank, const void* d_spec, int64_t nbins, int32_t t_begin,
+                       int32_t t_end, double k_sigma, double pre, double* d_stats, jerk_candidate* d_out,
+                       int64_t capacity, unsigned long long* d_count, int64_t staged, void* d_ws, size_t ws_bytes,
+                       hipStream_t stream);
+
 // Sets j.n_seg and returns the job's tile count (segments x template blocks).
 int64_t fft_job_tiles(FftJob& j, int32_t seg_len);
 // twiddles: exp(-2 pi i k / seg_len), k < seg_len (complex64, device).

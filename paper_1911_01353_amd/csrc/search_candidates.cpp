@@ -1,0 +1,181 @@
+// Matched filter and candidate selection in one pass (paper, section "Results":
+// the search is timed together with the mean and standard deviation of the plane
+// and a peak finder with a user threshold), without writing the plane.
+//
+// The threshold of a row, mean + k sigma, is known only once the whole row has
+// been computed, so each width group takes these steps on the stream:
+//   1. speculative FFT pass: per (row, segment) FP64 sum and sum of squares of
+//      the powers, the powers at both ends of the segment, and every interior
+//      peak above a level `pre` staged in its tile's own run of slots;
+//   2. finish: row mean, sigma, threshold; a row is flagged when its threshold
+//      lies below `pre` (its staged hits may miss candidates) or when one of its
+//      tiles had more hits than slots;
+//   3. filter: staged hits of unflagged rows above their row's threshold;
+//   4. edges: the first and last point of every (row, segment);
+//   5. exact FFT pass over the flagged rows only, with their final thresholds.
+// Every step is exact: with pre below every row's threshold (e.g. about (1 + k)
+// times the mean power of a noise row, scaled down a little) step 5 has no work,
+// and with any other pre the flagged rows are recomputed. The result equals the
+// plane written by jerk_search followed by jerk_plane_stats and
+// jerk_find_candidates, up to the rounding of the FP64 statistics.
+//
+// Staging slots per tile (tpb templates x 2U points): the caller's number, or
+// by default 2 exp(-pre) of the tile's points plus 16, the expected share of
+// points above pre on a spectrum of unit mean power being exp(-pre). Never more
+// than tpb U, the most peaks a tile can hold (peaks are never adjacent). Tiles
+// with more hits (a strong signal leaks high powers into the r range around it
+// in every template) spill into a shared pool of half the slots (plus 2^16 with
+// the default slot count); only a hit that finds the pool full flags its row.
+#include <algorithm>
+#include <cmath>
+
+#include "jerk_internal.h"
+
+namespace jerk {
+namespace {
+
+struct CandLayout {
+  size_t part = 0, edge = 0, rs = 0, flagged = 0, n_flagged = 0, ovf = 0, tile_hits = 0, hits = 0, pool = 0,
+         total = 0;
+  int64_t pool_cap = 0;
+};
+
+void group_range(const Group& g, int32_t t_begin, int32_t t_end, int32_t* lo, int32_t* hi) {
+  *lo = (int32_t)(std::lower_bound(g.members.begin(), g.members.end(), t_begin) - g.members.begin());
+  *hi = (int32_t)(std::lower_bound(g.members.begin(), g.members.end(), t_end) - g.members.begin());
+}
+
+int64_t group_segments(const Group& g, int64_t nbins) {
+  const int64_t U = g.seg_len - g.taps + 1;
+  return (nbins + U - 1) / U;
+}
+
+int64_t group_tiles(const Group& g, int32_t rows, int64_t nbins) {
+  return (int64_t)((rows + g.tpb - 1) / g.tpb) * group_segments(g, nbins);
+}
+
+int32_t group_cap(const Group& g, double pre, int64_t staged) {
+  const int64_t U = g.seg_len - g.taps + 1;
+  const int64_t most = (int64_t)g.tpb * U;
+  int64_t cap = staged;
+  if (cap <= 0) {
+    const double pts = 2.0 * (double)g.tpb * (double)U;
+    cap = (int64_t)std::ceil(2.0 * pts * std::exp(-std::max(0.0, pre))) + 16;
+  }
+  return (int32_t)std::min(cap, most);
+}
+
+CandLayout cand_layout(const Plan& p, int64_t nbins, int32_t t_begin, int32_t t_end, double pre, int64_t staged) {
+  int64_t max_rs = 0, max_rows = 0, max_tiles = 0, max_slots = 0;
+  for (const Group& g : p.groups) {
+    int32_t lo, hi;
+    group_range(g, t_begin, t_end, &lo, &hi);
+    if (lo >= hi) continue;
+    max_rows = std::max<int64_t>(max_rows, hi - lo);
+    max_rs = std::max<int64_t>(max_rs, (int64_t)(hi - lo) * group_segments(g, nbins));
+    const int64_t tiles = group_tiles(g, hi - lo, nbins);
+    max_tiles = std::max(max_tiles, tiles);
+    max_slots = std::max(max_slots, tiles * group_cap(g, pre, staged));
+  }
+  CandLayout L;
+  L.part = 0;
+  L.edge = L.part + align_up((size_t)max_rs * sizeof(double2));
+  L.rs = L.edge + align_up((size_t)max_rs * 2 * sizeof(float2));
+  L.flagged = L.rs + align_up((size_t)max_rows * sizeof(CandRowStat));
+  L.n_flagged = L.flagged + align_up((size_t)max_rows * sizeof(int32_t));
+  L.ovf = L.n_flagged + kAlign;
+  L.tile_hits = L.ovf + align_up((size_t)max_rows * sizeof(int32_t));
+  L.hits = L.tile_hits + align_up((size_t)max_tiles * sizeof(uint32_t));
+  L.pool = L.hits + align_up((size_t)max_slots * sizeof(CandHit));
+  L.pool_cap = max_slots / 2 + (staged > 0 ? 0 : (int64_t(1) << 16));
+  L.total = L.pool + align_up((size_t)L.pool_cap * sizeof(CandPoolHit));
+  return L;
+}
+
+}  // namespace
+
+size_t search_candidates_workspace_bytes(const Plan& p, int64_t nbins, int32_t t_begin, int32_t t_end, double pre,
+                                         int64_t staged) {
+  return cand_layout(p, nbins, t_begin, t_end, pre, staged).total;
+}
+
+void search_candidates(const Plan& p, const void* d_bank, const void* d_spec, int64_t nbins, int32_t t_begin,
+                       int32_t t_end, double k_sigma, double pre, double* d_stats, jerk_candidate* d_out,
+                       int64_t capacity, unsigned long long* d_count, int64_t staged, void* d_ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  for (const Group& g : p.groups) {
+    int32_t lo, hi;
+    group_range(g, t_begin, t_end, &lo, &hi);
+    require(lo >= hi || g.path == JERK_PATH_FFT_FP32, JERK_EUNSUPPORTED,
+            "search with candidate selection runs on the FFT path: every width group in the range must use it");
+  }
+  const CandLayout L = cand_layout(p, nbins, t_begin, t_end, pre, staged);
+  require(ws_bytes >= L.total, JERK_ENOMEM, "search-candidates workspace too small");
+  char* ws = static_cast<char*>(d_ws);
+  double2* part = reinterpret_cast<double2*>(ws + L.part);
+  float2* edge = reinterpret_cast<float2*>(ws + L.edge);
+  CandRowStat* rs = reinterpret_cast<CandRowStat*>(ws + L.rs);
+  int32_t* flagged = reinterpret_cast<int32_t*>(ws + L.flagged);
+  uint32_t* n_flagged = reinterpret_cast<uint32_t*>(ws + L.n_flagged);
+  int32_t* ovf = reinterpret_cast<int32_t*>(ws + L.ovf);
+  uint32_t* tile_hits = reinterpret_cast<uint32_t*>(ws + L.tile_hits);
+  CandHit* hits = reinterpret_cast<CandHit*>(ws + L.hits);
+  CandPoolHit* pool = reinterpret_cast<CandPoolHit*>(ws + L.pool);
+  unsigned long long* pool_count = reinterpret_cast<unsigned long long*>(ws + L.n_flagged + 64);
+  const char* bank = static_cast<const char*>(d_bank);
+  const int32_t* members = reinterpret_cast<const int32_t*>(bank + p.off_members);
+  for (const Group& g : p.groups) {
+    int32_t lo, hi;
+    group_range(g, t_begin, t_end, &lo, &hi);
+    if (lo >= hi) continue;
+    FftJob j{};
+    j.spec = static_cast<const float2*>(d_spec);
+    j.nbins = nbins;
+    j.bank_fft = reinterpret_cast<const float2*>(bank + g.off_fft);
+    j.members = members + g.first_member;
+    j.m_begin = lo;
+    j.m_end = hi;
+    j.t_begin = t_begin;
+    j.row_by_member = 1;
+    j.row_base = lo;
+    j.taps = g.taps;
+    j.tpb = g.tpb;
+    const int32_t U = g.seg_len - g.taps + 1;
+    const int64_t n_seg = group_segments(g, nbins);
+    const int32_t rows = hi - lo;
+    const int32_t* row_t = j.members + lo;  // template of row r
+    const float2* tw = reinterpret_cast<const float2*>(bank + p.off_tw[tw_slot(g.seg_len)]);
+    require(g.tpb <= 65535 && 2 * (int64_t)U <= 65536, JERK_EINTERNAL, "tile too large for the hit encoding");
+    const int32_t cap = group_cap(g, pre, staged);
+    const int64_t tiles = group_tiles(g, rows, nbins);
+    require(tiles < (int64_t(1) << 31) && n_seg < (int64_t(1) << 31), JERK_EINVAL,
+            "search too large for one launch; split the template range");
+    CandArgs ca{};
+    ca.pre = pre;
+    ca.part = part;
+    ca.edge = edge;
+    ca.hits = hits;
+    ca.tile_hits = tile_hits;
+    ca.pool = pool;
+    ca.pool_count = pool_count;
+    ca.pool_cap = L.pool_cap;
+    ca.ovf = ovf;
+    ca.cap_tile = cap;
+    ca.rs = rs;
+    ca.flagged = flagged;
+    ca.n_flagged = n_flagged;
+    ca.out = d_out;
+    ca.capacity = capacity;
+    ca.count = d_count;
+    cand_reset(ovf, rows, n_flagged, pool_count, stream);
+    fft_cand_launch(j, g.seg_len, g.ept, tw, ca, 1, stream);
+    cand_finish(part, rows, n_seg, U, nbins, ovf, k_sigma, pre, row_t, t_begin, d_stats, rs, flagged, n_flagged,
+                stream);
+    cand_filter(hits, tile_hits, (int32_t)tiles, cap, (int32_t)n_seg, g.tpb, U, pool, pool_count, L.pool_cap, rs,
+                row_t, d_out, capacity, d_count, stream);
+    cand_edges(edge, rows, n_seg, U, nbins, rs, row_t, d_out, capacity, d_count, stream);
+    fft_cand_launch(j, g.seg_len, g.ept, tw, ca, 2, stream);
+  }
+}
+
+}  // namespace jerk

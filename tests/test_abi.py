@@ -198,3 +198,40 @@ def test_harmonic_shape_matches_the_oracle_and_validates():
     assert lib.jerk_harmonic_sum(plan.handle, one, 99, 100, 2, one, 100, None) == _lib.JERK_EINVAL
     assert lib.jerk_harmonic_sum(plan.handle, one, 100, 100, 2, one, 49, None) == _lib.JERK_EINVAL
     plan.close()
+
+
+def test_search_candidates_validates_on_the_host():
+    """Argument, path and workspace errors of the fused search are decided before any device call."""
+    import ctypes as C
+    from paper_1911_01353_amd import _lib
+    lib = _lib.load()
+    one = C.c_void_p(1)
+    plan = J.Plan(4096, 20.0, 60.0, 2.0, 20.0, path="fft")
+    T = plan.info()["n_templates"]
+    wsb = lib.jerk_search_candidates_workspace_bytes
+    assert wsb(None, 4096, 0, T, 2.7, 0) == 0
+    assert wsb(plan.handle, 0, 0, T, 2.7, 0) == 0
+    assert wsb(plan.handle, 4096, 0, T + 1, 2.7, 0) == 0
+    assert wsb(plan.handle, 4096, 0, T, 2.7, -1) == 0
+    assert wsb(plan.handle, 4096, 0, T, float("nan"), 0) == 0
+    small = wsb(plan.handle, 4096, 0, T, 50.0, 0)
+    assert small > 0
+    assert wsb(plan.handle, 4096, 0, T, 0.0, 0) > small           # a low level stages more
+    assert wsb(plan.handle, 4096, 0, T, 50.0, 1000) > wsb(plan.handle, 4096, 0, T, 50.0, 1) > 0  # slots per tile
+    assert wsb(plan.handle, 1 << 20, 0, T, 50.0, 0) > small
+    f = lib.jerk_search_candidates
+
+    def call(p=plan.handle, bank=one, spec=one, n=4096, tb=0, te=T, k=2.0, pre=2.7, staged=0, out=one, cap=10,
+             count=one, ws=one, wsn=1 << 40):
+        return f(p, bank, spec, n, tb, te, k, pre, staged, None, out, cap, count, ws, wsn, None)
+
+    assert call(tb=5, te=5, bank=None, spec=None, out=None, count=None, ws=None) == _lib.JERK_OK
+    assert call(p=None) == _lib.JERK_EINVAL
+    assert call(tb=-1) == _lib.JERK_EINVAL and call(te=T + 1) == _lib.JERK_EINVAL
+    assert call(n=0) == _lib.JERK_EINVAL and call(n=1 << 31) == _lib.JERK_EINVAL
+    assert call(k=float("nan")) == _lib.JERK_EINVAL and call(pre=float("inf")) == _lib.JERK_EINVAL
+    assert call(staged=-1) == _lib.JERK_EINVAL and call(cap=-1) == _lib.JERK_EINVAL
+    assert call(out=None) == _lib.JERK_EINVAL and call(count=None) == _lib.JERK_EINVAL
+    assert call(wsn=16) == _lib.JERK_ENOMEM
+    mfma = J.Plan(4096, 20.0, 60.0, 2.0, 20.0, path="split_bf16")
+    assert call(p=mfma.handle, te=mfma.info()["n_templates"]) == _lib.JERK_EUNSUPPORTED
