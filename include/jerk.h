@@ -305,8 +305,9 @@ int32_t jerk_find_candidates(const float* d_plane, int64_t ld, int32_t rows, int
 /* ---- search with candidate selection, no plane ---------------------------------
  * The matched filter of jerk_search and the selection of jerk_plane_stats +
  * jerk_find_candidates in one call that never writes the plane (the paper times the
- * filter together with this selection, section "Results"). Rows [t_begin, t_end), every
- * width group in the range on the FFT path.
+ * filter together with this selection, section "Results"). Rows [t_begin, t_end).
+ * Width groups on an MFMA path (no FFT bank) go through plane slabs of at most 2^30 bytes
+ * inside the workspace: search, jerk_plane_stats, jerk_find_candidates. The rest:
  *
  * The threshold mean + k_sigma * sigma of a row is known only after the whole row, so the
  * call runs per width group: a speculative pass that accumulates each row's sum and sum
@@ -328,8 +329,7 @@ int32_t jerk_find_candidates(const float* d_plane, int64_t ld, int32_t rows, int
  * Candidates are appended to d_out as by jerk_find_candidates (t = template index, count
  * in *d_count, which the caller clears first; order unspecified; capacity overflow counted).
  * EINVAL for a bad range, nbins outside [1, 2^31), non-finite k_sigma or pre_level, a
- * negative staged or capacity, or NULL pointers; EUNSUPPORTED when a group in the range
- * is on an MFMA path; ENOMEM for a workspace smaller than
+ * negative staged or capacity, or NULL pointers; ENOMEM for a workspace smaller than
  * jerk_search_candidates_workspace_bytes (0 for invalid arguments). Asynchronous on stream. */
 size_t jerk_search_candidates_workspace_bytes(const jerk_plan* plan, int64_t nbins, int32_t t_begin, int32_t t_end,
                                               double pre_level, int64_t staged);

@@ -476,7 +476,25 @@ __global__ void __launch_bounds__(256) cand_edges_kernel(const float2* __restric
   }
 }
 
+__global__ void __launch_bounds__(256) scatter_row_stats_kernel(const double* __restrict__ stats, int32_t rows,
+                                                                const int32_t* __restrict__ members, int32_t t_begin,
+                                                                double* __restrict__ out) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= rows) return;
+  const int64_t o = 2 * (int64_t)(members[i] - t_begin);
+  out[o] = stats[2 * (int64_t)i];
+  out[o + 1] = stats[2 * (int64_t)i + 1];
+}
+
 }  // namespace
+
+void scatter_row_stats(const double* stats, int32_t rows, const int32_t* d_members, int32_t t_begin, double* out,
+                       hipStream_t stream) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(scatter_row_stats_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream, stats,
+                     rows, d_members, t_begin, out);
+  JERK_HIP_CHECK(hipGetLastError());
+}
 
 void cand_reset(int32_t* ovf, int32_t rows, uint32_t* n_flagged, unsigned long long* pool_count, hipStream_t stream) {
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(1024, ((int64_t)rows + 255) / 256));

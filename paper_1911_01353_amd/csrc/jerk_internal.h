@@ -167,6 +167,12 @@ void cand_filter(const CandHit* hits, const uint32_t* tile_hits, int32_t tiles, 
 void cand_edges(const float2* edge, int32_t rows, int64_t n_seg, int32_t U, int64_t nbins, const CandRowStat* rs,
                 const int32_t* d_members, jerk_candidate* out, int64_t capacity, unsigned long long* count,
                 hipStream_t stream);
+// (row mean, sigma) of slab rows [rows][2] to out[2 (members[i] - t_begin)]
+void scatter_row_stats(const double* stats, int32_t rows, const int32_t* d_members, int32_t t_begin, double* out,
+                       hipStream_t stream);
+// capi.cpp: rows [m_begin, m_end) of group gi's member list into d_plane (row = member - m_begin)
+void search_members_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64_t nbins, float* d_plane,
+                            int64_t ld, int32_t gi, int32_t m_begin, int32_t m_end, hipStream_t stream);
 // search_candidates.cpp
 size_t search_candidates_workspace_bytes(const Plan& p, int64_t nbins, int32_t t_begin, int32_t t_end, double pre,
                                          int64_t staged);

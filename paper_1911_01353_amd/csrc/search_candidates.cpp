@@ -13,6 +13,9 @@
 //   3. filter: staged hits of unflagged rows above their row's threshold;
 //   4. edges: the first and last point of every (row, segment);
 //   5. exact FFT pass over the flagged rows only, with their final thresholds.
+// Width groups on an MFMA path have no FFT bank; their rows go through plane
+// slabs of at most 2^30 bytes in the workspace instead: search, row statistics,
+// peak finder (the two-step path, whose result this call equals).
 // Every step is exact: with pre below every row's threshold (e.g. about (1 + k)
 // times the mean power of a noise row, scaled down a little) step 5 has no work,
 // and with any other pre the flagged rows are recomputed. The result equals the
@@ -36,9 +39,19 @@ namespace {
 
 struct CandLayout {
   size_t part = 0, edge = 0, rs = 0, flagged = 0, n_flagged = 0, ovf = 0, tile_hits = 0, hits = 0, pool = 0,
-         total = 0;
+         slab = 0, slab_stats = 0, slab_ws = 0, total = 0;
   int64_t pool_cap = 0;
+  int32_t slab_rows = 0;  // rows per plane slab of an MFMA-path group
+  int64_t slab_ld = 0;
 };
+
+// Rows of an MFMA-path group searched per plane slab: a multiple of 8 (a row
+// block of the MFMA kernel) and at most 2^30 bytes of plane.
+int32_t slab_rows_for(int64_t nbins) {
+  const int64_t ld = (2 * nbins + 3) / 4 * 4;
+  const int64_t r = ((int64_t(1) << 30) / (ld * 4)) / 8 * 8;
+  return (int32_t)std::max<int64_t>(8, std::min<int64_t>(r, 1 << 20));
+}
 
 void group_range(const Group& g, int32_t t_begin, int32_t t_end, int32_t* lo, int32_t* hi) {
   *lo = (int32_t)(std::lower_bound(g.members.begin(), g.members.end(), t_begin) - g.members.begin());
@@ -66,11 +79,16 @@ int32_t group_cap(const Group& g, double pre, int64_t staged) {
 }
 
 CandLayout cand_layout(const Plan& p, int64_t nbins, int32_t t_begin, int32_t t_end, double pre, int64_t staged) {
-  int64_t max_rs = 0, max_rows = 0, max_tiles = 0, max_slots = 0;
+  int64_t max_rs = 0, max_rows = 0, max_tiles = 0, max_slots = 0, max_slab = 0;
+  const int32_t sr = slab_rows_for(nbins);
   for (const Group& g : p.groups) {
     int32_t lo, hi;
     group_range(g, t_begin, t_end, &lo, &hi);
     if (lo >= hi) continue;
+    if (g.path != JERK_PATH_FFT_FP32) {
+      max_slab = std::max<int64_t>(max_slab, std::min<int64_t>(sr, hi - lo));
+      continue;
+    }
     max_rows = std::max<int64_t>(max_rows, hi - lo);
     max_rs = std::max<int64_t>(max_rs, (int64_t)(hi - lo) * group_segments(g, nbins));
     const int64_t tiles = group_tiles(g, hi - lo, nbins);
@@ -88,7 +106,12 @@ CandLayout cand_layout(const Plan& p, int64_t nbins, int32_t t_begin, int32_t t_
   L.hits = L.tile_hits + align_up((size_t)max_tiles * sizeof(uint32_t));
   L.pool = L.hits + align_up((size_t)max_slots * sizeof(CandHit));
   L.pool_cap = max_slots / 2 + (staged > 0 ? 0 : (int64_t(1) << 16));
-  L.total = L.pool + align_up((size_t)L.pool_cap * sizeof(CandPoolHit));
+  L.slab_rows = (int32_t)max_slab;
+  L.slab_ld = (2 * nbins + 3) / 4 * 4;
+  L.slab = L.pool + align_up((size_t)L.pool_cap * sizeof(CandPoolHit));
+  L.slab_stats = L.slab + align_up((size_t)max_slab * (size_t)L.slab_ld * sizeof(float));
+  L.slab_ws = L.slab_stats + align_up((size_t)max_slab * 2 * sizeof(double));
+  L.total = L.slab_ws + align_up(max_slab > 0 ? stats_workspace_bytes((int32_t)max_slab, 2 * nbins) : 0);
   return L;
 }
 
@@ -103,12 +126,6 @@ void search_candidates(const Plan& p, const void* d_bank, const void* d_spec, in
                        int32_t t_end, double k_sigma, double pre, double* d_stats, jerk_candidate* d_out,
                        int64_t capacity, unsigned long long* d_count, int64_t staged, void* d_ws, size_t ws_bytes,
                        hipStream_t stream) {
-  for (const Group& g : p.groups) {
-    int32_t lo, hi;
-    group_range(g, t_begin, t_end, &lo, &hi);
-    require(lo >= hi || g.path == JERK_PATH_FFT_FP32, JERK_EUNSUPPORTED,
-            "search with candidate selection runs on the FFT path: every width group in the range must use it");
-  }
   const CandLayout L = cand_layout(p, nbins, t_begin, t_end, pre, staged);
   require(ws_bytes >= L.total, JERK_ENOMEM, "search-candidates workspace too small");
   char* ws = static_cast<char*>(d_ws);
@@ -124,10 +141,27 @@ void search_candidates(const Plan& p, const void* d_bank, const void* d_spec, in
   unsigned long long* pool_count = reinterpret_cast<unsigned long long*>(ws + L.n_flagged + 64);
   const char* bank = static_cast<const char*>(d_bank);
   const int32_t* members = reinterpret_cast<const int32_t*>(bank + p.off_members);
-  for (const Group& g : p.groups) {
+  float* slab = reinterpret_cast<float*>(ws + L.slab);
+  double* slab_stats = reinterpret_cast<double*>(ws + L.slab_stats);
+  void* slab_ws = ws + L.slab_ws;
+  const size_t slab_ws_bytes = L.total - L.slab_ws;
+  for (int32_t gi = 0; gi < (int32_t)p.groups.size(); ++gi) {
+    const Group& g = p.groups[gi];
     int32_t lo, hi;
     group_range(g, t_begin, t_end, &lo, &hi);
     if (lo >= hi) continue;
+    if (g.path != JERK_PATH_FFT_FP32) {
+      const int32_t* gm = members + g.first_member;
+      for (int32_t m0 = lo; m0 < hi; m0 += L.slab_rows) {
+        const int32_t m1 = std::min(hi, m0 + L.slab_rows);
+        search_members_enqueue(p, d_bank, d_spec, nbins, slab, L.slab_ld, gi, m0, m1, stream);
+        plane_stats(slab, L.slab_ld, m1 - m0, 2 * nbins, slab_stats, slab_ws, slab_ws_bytes, stream);
+        find_candidates(slab, L.slab_ld, m1 - m0, 2 * nbins, slab_stats, k_sigma, gm + m0, 0, d_out, capacity, d_count,
+                        stream);
+        if (d_stats) scatter_row_stats(slab_stats, m1 - m0, gm + m0, t_begin, d_stats, stream);
+      }
+      continue;
+    }
     FftJob j{};
     j.spec = static_cast<const float2*>(d_spec);
     j.nbins = nbins;

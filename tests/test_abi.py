@@ -234,4 +234,8 @@ def test_search_candidates_validates_on_the_host():
     assert call(out=None) == _lib.JERK_EINVAL and call(count=None) == _lib.JERK_EINVAL
     assert call(wsn=16) == _lib.JERK_ENOMEM
     mfma = J.Plan(4096, 20.0, 60.0, 2.0, 20.0, path="split_bf16")
-    assert call(p=mfma.handle, te=mfma.info()["n_templates"]) == _lib.JERK_EUNSUPPORTED
+    Tm = mfma.info()["n_templates"]
+    slab = wsb(mfma.handle, 4096, 0, Tm, 2.7, 0)
+    biggest = max(g["n_members"] for g in mfma.groups())
+    assert slab >= biggest * 2 * 4096 * 4     # MFMA groups go through a plane slab (a whole group fits)
+    assert call(p=mfma.handle, te=Tm, wsn=slab - 1) == _lib.JERK_ENOMEM

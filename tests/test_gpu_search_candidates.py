@@ -208,20 +208,50 @@ def test_capacity_overflow_counts_everything(fft_plan):
     assert {(int(r["t"]), int(r["p"])) for r in part} <= keys
 
 
-def test_rejects_mfma_groups_and_short_workspace():
+@pytest.mark.parametrize("path", ["split_bf16", "fp16", "auto"])
+def test_mfma_groups_through_plane_slabs(path):
+    """Groups on an MFMA path go through plane slabs; the result equals the two-step path."""
+    device()
+    n = 20000
+    plan = J.Plan(n, 20.0, 60.0, 2.0, 20.0, path=path)
+    bank = build_bank(plan)
+    spec = _spectrum(n, 77, tone=(5000, 10.0))
+    k = 2.0
+    plane, stats, want = _two_step(plan, bank, spec, k)
+    for pre in (0.9 * (1 + k), 1e9):
+        st, got, _ = _fused(plan, bank, spec, k, pre)
+        assert np.all(np.abs(st - stats) <= 1e-12 * np.maximum(np.abs(stats), 1e-30))
+        _same(got, want, plane, stats, k)
+    st, got, _ = _fused(plan, bank, spec, k, 0.9 * (1 + k), 0, 30, 101)
+    _same(got, want[(want["t"] >= 30) & (want["t"] < 101)], plane[30:101], stats[30:101], k, t_begin=30)
+
+
+def test_mixed_fft_and_mfma_groups():
+    """A plan whose groups are split between the FFT and the split-BF16 paths."""
+    device()
+    n = 30011
+    plan = J.Plan(n, 20.0, 60.0, 2.0, 20.0, path="fft")
+    for g in range(plan.info()["n_groups"]):
+        gi = plan.group(g)
+        plan.set_group(g, gi["seg_len"], gi["templates_per_block"], "split_bf16" if g % 2 else "fft",
+                       gi["fft_ept"])
+    bank = build_bank(plan)
+    spec = _spectrum(n, 78)
+    k = 1.5
+    plane, stats, want = _two_step(plan, bank, spec, k)
+    st, got, _ = _fused(plan, bank, spec, k, 0.9 * (1 + k))
+    _same(got, want, plane, stats, k)
+
+
+def test_short_workspace():
     import torch
     dev = device()
-    plan = J.Plan(4096, 20.0, 60.0, 2.0, 20.0, path="split_bf16")
+    plan = J.Plan(4096, 20.0, 60.0, 2.0, 20.0, path="fft")
     bank = build_bank(plan)
     spec = torch.zeros(4096, dtype=torch.complex64, device=dev)
     out = torch.zeros((16, 4), dtype=torch.int32, device=dev)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
-    with pytest.raises(J.JerkError) as ei:
-        plan.search_candidates(bank, spec, 2.0, 2.7, out, count)
-    assert ei.value.status == _lib.JERK_EUNSUPPORTED
-    plan2 = J.Plan(4096, 20.0, 60.0, 2.0, 20.0, path="fft")
-    bank2 = build_bank(plan2)
     ws = torch.empty(16, dtype=torch.uint8, device=dev)
     with pytest.raises(J.JerkError) as ei:
-        plan2.search_candidates(bank2, spec, 2.0, 2.7, out, count, ws=ws)
+        plan.search_candidates(bank, spec, 2.0, 2.7, out, count, ws=ws)
     assert ei.value.status == J.JERK_ENOMEM
