@@ -754,7 +754,10 @@ def main():
     kernel_share = d["time"] / sum(v["time"] for v in ks.values())
     if d["path"] == 0:
         achieved = d["flops"] / d["launches"] / avg_t / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_TFLOPS, "unit": "TFLOP/s"}
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "peak_note": "non-packed FP32 FMA rate (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz); packed FP32 "
+                             "instructions are disabled in all device code",
+                "frac_of_packed_157_3": achieved / 157.3}
     else:
         achieved = d["flops"] / d["launches"] / avg_t / 1e12
         roof = {"bound": "mfma", "achieved": achieved,
