@@ -255,3 +255,77 @@ def test_short_workspace():
     with pytest.raises(J.JerkError) as ei:
         plan.search_candidates(bank, spec, 2.0, 2.7, out, count, ws=ws)
     assert ei.value.status == J.JERK_ENOMEM
+
+
+def test_full_size_sampled_rows():
+    """The 2^22-bin search (12261 templates, zmax 200, wmax 600) with fused selection in the bench's
+    configuration (autotuned FFT plan, k = 6, speculative level 6.3), checked on whole rows: two
+    corners, the centre and the templates nearest two injected tones. Each row's candidates and
+    statistics against the library's two-step path on that row (exact bar) and against the FP64
+    oracle's row (every disagreement at a decision within the plane's error)."""
+    import torch
+    dev = device()
+    cfg = synth.CONFIGS["bins2e22_z200_w600"]
+    spec_np = synth.make_spectrum(cfg)
+    n = spec_np.shape[0]
+    spec = torch.from_numpy(spec_np).to(dev)
+    plan = J.Plan(n, cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path="fft")
+    plan.autotune(spec)
+    bank = build_bank(plan)
+    T = plan.info()["n_templates"]
+    k, pre = 6.0, 6.3
+    out = torch.zeros((1 << 27, 4), dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    stats = torch.empty((T, 2), dtype=torch.float64, device=dev)
+    plan.search_candidates(bank, spec, k, pre, out, count, stats=stats)
+    torch.cuda.synchronize()
+    total = int(count.item())
+    assert 0 < total <= out.shape[0]
+    grid = Grid(cfg.zmax, cfg.wmax, cfg.dz, cfg.dw)
+    n_z, J_w = grid.n_z, int(cfg.wmax // cfg.dw)
+    tone_rows = []
+    for tone in cfg.tones[:2]:
+        zb, w = tone.z0 + tone.w0 / 2, tone.w0
+        i = int(round((zb + cfg.zmax) / cfg.dz))
+        j = int(round(w / cfg.dw)) + J_w
+        tone_rows.append(j * n_z + i)
+    rows = [0, T - 1, T // 2] + tone_rows
+    sel = out[:total][torch.isin(out[:total, 0], torch.tensor(rows, dtype=torch.int32, device=dev))]
+    got_all = np.sort(sel.cpu().numpy().view(J.CANDIDATE_DTYPE).reshape(-1), order=["t", "p"])
+    st_all = stats.cpu().numpy()
+    plane_row = torch.empty((1, 2 * n), dtype=torch.float32, device=dev)
+    row_stats = torch.empty((1, 2), dtype=torch.float64, device=dev)
+    ws = torch.empty(max(1, J.stats_workspace_bytes(1, 2 * n)), dtype=torch.uint8, device=dev)
+    for t in rows:
+        got = got_all[got_all["t"] == t]
+        # two-step path on this row
+        plan.search(bank, spec, plane_row, t, t + 1)
+        J.plane_stats(plane_row, row_stats, ws=ws)
+        o2 = torch.zeros((1 << 20, 4), dtype=torch.int32, device=dev)
+        c2 = torch.zeros(1, dtype=torch.int64, device=dev)
+        J.find_candidates(plane_row, row_stats, k, o2, c2, t_base=t)
+        torch.cuda.synchronize()
+        want2 = J.candidates_numpy(o2, c2)
+        gp = plane_row.cpu().numpy()
+        gs = row_stats.cpu().numpy()
+        assert np.all(np.abs(st_all[t] - gs[0]) <= 1e-12 * np.abs(gs[0])), t
+        _same(got, want2, gp, gs, k, t_begin=t)
+        # FP64 oracle row
+        ora = oracle_plane(spec_np, grid, templates=[t])[0]
+        ost = row_statistics(ora.astype(np.float32)[None, :])[0]
+        assert np.all(np.abs(st_all[t] - ost) <= 1e-4 * ost), (t, st_all[t], ost)
+        want = find_candidates(ora.astype(np.float32)[None, :], k, row_template=[t])
+        g = {int(r["p"]) for r in got}
+        w = {int(r["p"]) for r in want}
+        thr = ost[0] + k * ost[1]
+        for p in g ^ w:
+            tol = 2e-4 * max(float(ora[p]), ost[0])
+            near = abs(ora[p] - thr) <= tol + 1e-4 * k * ost[1]
+            near |= p > 0 and abs(ora[p] - ora[p - 1]) <= tol
+            near |= p + 1 < ora.shape[0] and abs(ora[p] - ora[p + 1]) <= tol
+            assert near, ("candidate disagrees with the oracle away from any boundary", t, p)
+        assert len(g ^ w) <= max(2, len(w) // 100), (t, len(g ^ w), len(w))
+        if t in tone_rows:
+            best = got[np.argmax(got["power"])]
+            assert int(best["p"]) == int(np.argmax(ora)), (t, int(best["p"]), int(np.argmax(ora)))
+    plan.close()
