@@ -190,7 +190,7 @@ __device__ __forceinline__ uint64_t peak_key(float power, int64_t p) {
 //   no device-wide atomics, and none at all when the workgroup is one wave);
 //   hits past the run go to the shared pool (one atomic per wave and template),
 //   and a hit that finds the pool full marks its row in ca.ovf.
-// The wave takes its peaks of all columns first and reserves their slots once.
+// The wave finds its peaks of all columns first and reserves their slots once.
 //   Mode 2 (exact): appends the interior peaks above the row's final threshold
 //   to the candidate list.
 template <int S, int E, int R1, int CAND>
@@ -220,20 +220,9 @@ __device__ __forceinline__ void cand_epilogue(const CandArgs& ca, const FftJob& 
     s = wave_sum_f64(s);
     q = wave_sum_f64(q);
   }
-  // fl[c]: P1 one lag left of lane 0's lag in column c; fr[c]: P0 one lag right of lane 63's.
-  float fl[E], fr[E];
-  if constexpr (W == 1) {
-#pragma unroll
-    for (int c = 0; c < E; ++c) {
-      fl[c] = c > 0 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(P1[((c - 1) % M) * R1 + (c - 1) / M]), 63))
-                    : 0.0f;
-      fr[c] = c + 1 < E
-                  ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(P0[((c + 1) % M) * R1 + (c + 1) / M]), 0))
-                  : 0.0f;
-    }
-  } else {
-    float* xl = xch;          // [W][E]: P1 of lane 63 of each wave
-    float* xr = xch + W * E;  // [W][E]: P0 of lane 0 of each wave
+  float* xl = xch;          // [W][E]: P1 of lane 63 of each wave (W > 1)
+  float* xr = xch + W * E;  // [W][E]: P0 of lane 0 of each wave
+  if constexpr (W > 1) {
     if (lane == 63) {
 #pragma unroll
       for (int c = 0; c < E; ++c) xl[wave * E + c] = P1[(c % M) * R1 + c / M];
@@ -244,11 +233,6 @@ __device__ __forceinline__ void cand_epilogue(const CandArgs& ca, const FftJob& 
       if constexpr (CAND == 1) wsum[wave] = make_double2(s, q);
     }
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < E; ++c) {
-      fl[c] = wave > 0 ? xl[(wave - 1) * E + c] : (c > 0 ? xl[(W - 1) * E + c - 1] : 0.0f);
-      fr[c] = wave + 1 < W ? xr[(wave + 1) * E + c] : (c + 1 < E ? xr[c + 1] : 0.0f);
-    }
     if constexpr (CAND == 1) {
       if (tid == 0) {
         s = wsum[0].x;
@@ -261,6 +245,22 @@ __device__ __forceinline__ void cand_epilogue(const CandArgs& ca, const FftJob& 
       }
     }
   }
+  // P1 one lag left of lane 0's lag in column c, and P0 one lag right of lane 63's
+  auto fill_left = [&](int c) -> float {
+    if constexpr (W == 1)
+      return c > 0 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(P1[((c - 1) % M) * R1 + (c - 1) / M]), 63))
+                   : 0.0f;
+    else
+      return wave > 0 ? xl[(wave - 1) * E + c] : (c > 0 ? xl[(W - 1) * E + c - 1] : 0.0f);
+  };
+  auto fill_right = [&](int c) -> float {
+    if constexpr (W == 1)
+      return c + 1 < E
+                 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(P0[((c + 1) % M) * R1 + (c + 1) / M]), 0))
+                 : 0.0f;
+    else
+      return wave + 1 < W ? xr[(wave + 1) * E + c] : (c + 1 < E ? xr[c + 1] : 0.0f);
+  };
   double thr, mean = 0.0, sigma = 0.0;
   if constexpr (CAND == 1) {
     thr = ca.pre;
@@ -286,24 +286,34 @@ __device__ __forceinline__ void cand_epilogue(const CandArgs& ca, const FftJob& 
   // For a float x, (double) x > thr exactly when x > thr rounded down to a float.
   const float thr_f = __double2float_rd(thr);
   const int64_t pbase = 2 * (seg * U);
-  uint64_t hm[E], h1m[E];  // per column: lanes with a peak, lanes whose peak is the phase-1 point
-  uint32_t total = 0;
+  // Bit c of hits: this lane's column c holds a peak; of ph1: that peak is the phase-1 point
+  // (never both points: a phase-0 peak needs P0 >= P1, a phase-1 peak P1 > P0).
+  uint32_t hits = 0u, ph1 = 0u;
 #pragma unroll
   for (int c = 0; c < E; ++c) {
     const int e = (c % M) * R1 + c / M;
     const float a = P0[e], b = P1[e];
-    const float left = dpp_f32<0x138>(fl[c], b);   // lane i reads P1 of lane i - 1
-    const float right = dpp_f32<0x130>(fr[c], a);  // lane i reads P0 of lane i + 1
+    const float left = dpp_f32<0x138>(fill_left(c), b);   // lane i reads P1 of lane i - 1
+    const float right = dpp_f32<0x130>(fill_right(c), a);  // lane i reads P0 of lane i + 1
     const int lag = tid + TPB * c;
     const bool h0 = lag > 0 && lag < lag_lim && a > left && a >= b && a > thr_f;
     const bool h1 = lag + 1 < lag_lim && b > a && b >= right && b > thr_f;
-    hm[c] = __ballot(h0 || h1);  // never both: h0 needs a >= b, h1 needs b > a
-    h1m[c] = __ballot(h1);
-    total += (uint32_t)__popcll(hm[c]);
+    hits |= (uint32_t)(h0 || h1) << c;
+    ph1 |= (uint32_t)h1 << c;
+  }
+  // The wave's total and this lane's exclusive prefix of the per-lane counts, from one ballot
+  // per bit of the count.
+  const uint32_t cnt = (uint32_t)__popc(hits);
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t total = 0u, prefix = 0u;
+#pragma unroll
+  for (int bit = 0; (1 << bit) <= E; ++bit) {
+    const uint64_t m = __ballot((cnt >> bit) & 1u);
+    total += (uint32_t)__popcll(m) << bit;
+    prefix += (uint32_t)__popcll(m & below) << bit;
   }
   if (total == 0u) return;  // wave-uniform
-  const uint64_t below = (1ull << lane) - 1ull;
-  // one reservation for all the wave's peaks of this template
+  // one reservation for all the wave's peaks of this template; lane order, then column order
   if constexpr (CAND == 1) {
     uint32_t base;
     if constexpr (W == 1) {
@@ -324,41 +334,37 @@ __device__ __forceinline__ void cand_epilogue(const CandArgs& ca, const FftJob& 
       const int hi = __builtin_amdgcn_readlane((int)(p0 >> 32), 0);
       pb = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
     }
-    uint32_t run = base;
+    uint32_t i = base + prefix;
 #pragma unroll
     for (int c = 0; c < E; ++c) {
-      if (hm[c] == 0ull) continue;  // wave-uniform
-      if ((hm[c] >> lane) & 1ull) {
+      if ((hits >> c) & 1u) {
         const int e = (c % M) * R1 + c / M;
-        const bool h1 = (h1m[c] >> lane) & 1ull;
+        const bool h1 = (ph1 >> c) & 1u;
         const uint32_t poff = (uint32_t)(2 * (tid + TPB * c) + (h1 ? 1 : 0));
         const float pw = h1 ? P1[e] : P0[e];
-        const uint32_t i = run + (uint32_t)__popcll(hm[c] & below);
         if (i < cap) {
           ca.hits[(int64_t)blockIdx.x * cap + i] = CandHit{((uint32_t)(row - row0) << 16) | poff, pw};
         } else {
-          const unsigned long long q = pb + (i - first);
-          if (q < (unsigned long long)ca.pool_cap)
-            ca.pool[q] = CandPoolHit{(uint32_t)row, (uint32_t)pbase + poff, pw, 0u};
+          const unsigned long long qq = pb + (i - first);
+          if (qq < (unsigned long long)ca.pool_cap)
+            ca.pool[qq] = CandPoolHit{(uint32_t)row, (uint32_t)pbase + poff, pw, 0u};
           else
             ca.ovf[row] = 1;
         }
+        ++i;
       }
-      run += (uint32_t)__popcll(hm[c]);
     }
   } else {
     unsigned long long g0 = 0;
     if (lane == 0) g0 = atomicAdd(ca.count, (unsigned long long)total);
     const int lo = __builtin_amdgcn_readlane((int)(unsigned)(g0 & 0xffffffffull), 0);
     const int hi = __builtin_amdgcn_readlane((int)(g0 >> 32), 0);
-    unsigned long long run = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+    unsigned long long i = (((unsigned long long)(unsigned)hi << 32) | (unsigned)lo) + prefix;
 #pragma unroll
     for (int c = 0; c < E; ++c) {
-      if (hm[c] == 0ull) continue;  // wave-uniform
-      if ((hm[c] >> lane) & 1ull) {
+      if ((hits >> c) & 1u) {
         const int e = (c % M) * R1 + c / M;
-        const bool h1 = (h1m[c] >> lane) & 1ull;
-        const unsigned long long i = run + (unsigned long long)__popcll(hm[c] & below);
+        const bool h1 = (ph1 >> c) & 1u;
         if (i < (unsigned long long)ca.capacity) {
           jerk_candidate cd;
           cd.t = (uint32_t)t;
@@ -367,8 +373,8 @@ __device__ __forceinline__ void cand_epilogue(const CandArgs& ca, const FftJob& 
           cd.sigma = (float)(((double)cd.power - mean) / sigma);
           ca.out[i] = cd;
         }
+        ++i;
       }
-      run += (unsigned long long)__popcll(hm[c]);
     }
   }
 }
