@@ -58,6 +58,11 @@ def main():
     ap.add_argument("--bench-name", required=True)
     ap.add_argument("--points", type=float, required=True)
     ap.add_argument("--copy-mib", type=float, required=True)
+    ap.add_argument("--first", type=int, default=0,
+                    help="only the first N matching dispatches in dispatch order (0: all), e.g. when later "
+                         "parts of the profiled run launch the same kernel")
+    ap.add_argument("--algo-write", type=float, default=4.0,
+                    help="algorithmic bytes written per point, for the summary (4: the plane)")
     ap.add_argument("--command", default="")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"))
     a = ap.parse_args()
@@ -73,9 +78,14 @@ def main():
 
     fscale, fcopy = calib(fv, fn)
     wscale, wcopy = calib(wv, wn)
-    fk = sum(v for d, v in fv.items() if rx.search(fn[d]))
-    wk = sum(v for d, v in wv.items() if rx.search(wn[d]))
-    nk = sum(1 for d in fv if rx.search(fn[d]))
+    def pick(vals, names):
+        ds = sorted(d for d in vals if rx.search(names[d]))
+        return ds[: a.first] if a.first > 0 else ds
+
+    fd, wd = pick(fv, fn), pick(wv, wn)
+    fk = sum(fv[d] for d in fd)
+    wk = sum(wv[d] for d in wd)
+    nk = len(fd)
     fetch_b = fk * 1024.0 * fscale
     write_b = wk * 1024.0 * wscale
     kind = "gemm" if "gemm" in a.bench_name else "fft"
@@ -100,7 +110,8 @@ def main():
                  f" WRITE_SIZE read {wcopy:.0f} KiB (scale {wscale:.3f})\n")
         fh.write(f"dispatches {nk}, algorithmic points {a.points:.4e}\n")
         fh.write(f"fetch  {fetch_b / 1e9:.3f} GB  = {fetch_b / a.points:.3f} B/point\n")
-        fh.write(f"write  {write_b / 1e9:.3f} GB  = {write_b / a.points:.3f} B/point (algorithmic write 4 B/point)\n")
+        fh.write(f"write  {write_b / 1e9:.3f} GB  = {write_b / a.points:.3f} B/point "
+                 f"(algorithmic write {a.algo_write:g} B/point)\n")
         fh.write(f"total  {(fetch_b + write_b) / a.points:.3f} B/point\n")
     print(json.dumps(ent))
 
