@@ -329,3 +329,23 @@ def test_full_size_sampled_rows():
             best = got[np.argmax(got["power"])]
             assert int(best["p"]) == int(np.argmax(ora)), (t, int(best["p"]), int(np.argmax(ora)))
     plan.close()
+
+
+def test_zero_spectrum_and_negative_k(fft_plan):
+    """A zero spectrum: every row constant 0 (sigma 0), every row flagged (threshold 0 below the
+    level) and recomputed, no candidates. A negative k puts the threshold below the mean: most
+    peaks are candidates, the staging slots overflow into the pool; still the two-step result."""
+    import torch
+    plan, bank = fft_plan
+    n = 1 << 15
+    zero = np.zeros(n, dtype=np.complex64)
+    st, got, count = _fused(plan, bank, zero, 3.0, 0.9 * 4.0)
+    assert count == 0 and len(got) == 0
+    assert np.all(st == 0.0)
+    spec = _spectrum(n, 21)
+    k = -0.5
+    plane, stats, want = _two_step(plan, bank, spec, k)
+    for pre, staged in [(0.2, 0), (2.0, 0)]:
+        st, got, _ = _fused(plan, bank, spec, k, pre, staged)
+        _same(got, want, plane, stats, k)
+    assert len(want) > plane.size // 8
