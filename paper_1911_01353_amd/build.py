@@ -65,7 +65,31 @@ def build(verbose: bool = True) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}", file=sys.stderr)
+    demo = build_c_demo()
+    if verbose:
+        print(f"built {demo}", file=sys.stderr)
     return LIB
+
+
+C_DEMO_SRC = os.path.join(HERE, "..", "tests", "c_abi", "jerk_demo.c")
+C_DEMO = os.path.join(HERE, "..", "tests", "c_abi", "jerk_demo")
+
+
+def build_c_demo() -> str:
+    """The C caller used by the tests (plain C against include/jerk.h and libjerk.so)."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(_hipcc())))
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        raise RuntimeError("a C compiler (gcc) is required to build the C demo")
+    cmd = [cc, "-O2", "-std=c11", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(HERE, "..", "include"), "-I", os.path.join(rocm, "include"),
+           C_DEMO_SRC, "-o", C_DEMO + ".tmp", "-L", HERE, "-ljerk", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN/../../paper_1911_01353_amd", "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"C demo build failed: {' '.join(cmd)}\n{res.stdout}{res.stderr}")
+    os.replace(C_DEMO + ".tmp", C_DEMO)
+    return os.path.normpath(C_DEMO)
 
 
 if __name__ == "__main__":

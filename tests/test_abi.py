@@ -239,3 +239,13 @@ def test_search_candidates_validates_on_the_host():
     biggest = max(g["n_members"] for g in mfma.groups())
     assert slab >= biggest * 2 * 4096 * 4     # MFMA groups go through a plane slab (a whole group fits)
     assert call(p=mfma.handle, te=Tm, wsn=slab - 1) == _lib.JERK_ENOMEM
+
+
+def test_plain_c_caller_is_built():
+    """The C caller of the GPU tests links against the library and rejects bad arguments before
+    any device call."""
+    import subprocess
+    demo = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c_abi", "jerk_demo")
+    assert os.path.exists(demo), "tests/c_abi/jerk_demo is missing: build the library first"
+    r = subprocess.run([demo], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 1 and "usage" in r.stderr
