@@ -6,10 +6,11 @@
 // been computed, so each width group takes these steps on the stream:
 //   1. speculative FFT pass: per (row, segment) FP64 sum and sum of squares of
 //      the powers, the powers at both ends of the segment, and every interior
-//      peak above a level `pre` staged in its tile's own run of slots;
+//      peak above a level `pre` staged in its tile's own run of slots or, past
+//      those, in a shared pool;
 //   2. finish: row mean, sigma, threshold; a row is flagged when its threshold
 //      lies below `pre` (its staged hits may miss candidates) or when one of its
-//      tiles had more hits than slots;
+//      hits found no room (tile slots and pool full);
 //   3. filter: staged hits of unflagged rows above their row's threshold;
 //   4. edges: the first and last point of every (row, segment);
 //   5. exact FFT pass over the flagged rows only, with their final thresholds.
@@ -46,7 +47,7 @@ struct CandLayout {
 };
 
 // Rows of an MFMA-path group searched per plane slab: a multiple of 8 (a row
-// block of the MFMA kernel) and at most 2^30 bytes of plane.
+// block of the MFMA kernel), at most 2^30 bytes of plane but never fewer than 8.
 int32_t slab_rows_for(int64_t nbins) {
   const int64_t ld = (2 * nbins + 3) / 4 * 4;
   const int64_t r = ((int64_t(1) << 30) / (ld * 4)) / 8 * 8;
@@ -126,6 +127,16 @@ void search_candidates(const Plan& p, const void* d_bank, const void* d_spec, in
                        int32_t t_end, double k_sigma, double pre, double* d_stats, jerk_candidate* d_out,
                        int64_t capacity, unsigned long long* d_count, int64_t staged, void* d_ws, size_t ws_bytes,
                        hipStream_t stream) {
+  // every check before anything is queued
+  for (const Group& g : p.groups) {
+    int32_t lo, hi;
+    group_range(g, t_begin, t_end, &lo, &hi);
+    if (lo >= hi || g.path != JERK_PATH_FFT_FP32) continue;
+    const int64_t U = g.seg_len - g.taps + 1;
+    require(g.tpb <= 65535 && 2 * U <= 65536, JERK_EINTERNAL, "tile too large for the hit encoding");
+    require(group_tiles(g, hi - lo, nbins) < (int64_t(1) << 31) && group_segments(g, nbins) < (int64_t(1) << 31),
+            JERK_EINVAL, "search too large for one launch; split the template range");
+  }
   const CandLayout L = cand_layout(p, nbins, t_begin, t_end, pre, staged);
   require(ws_bytes >= L.total, JERK_ENOMEM, "search-candidates workspace too small");
   char* ws = static_cast<char*>(d_ws);
@@ -179,11 +190,8 @@ void search_candidates(const Plan& p, const void* d_bank, const void* d_spec, in
     const int32_t rows = hi - lo;
     const int32_t* row_t = j.members + lo;  // template of row r
     const float2* tw = reinterpret_cast<const float2*>(bank + p.off_tw[tw_slot(g.seg_len)]);
-    require(g.tpb <= 65535 && 2 * (int64_t)U <= 65536, JERK_EINTERNAL, "tile too large for the hit encoding");
     const int32_t cap = group_cap(g, pre, staged);
     const int64_t tiles = group_tiles(g, rows, nbins);
-    require(tiles < (int64_t(1) << 31) && n_seg < (int64_t(1) << 31), JERK_EINVAL,
-            "search too large for one launch; split the template range");
     CandArgs ca{};
     ca.pre = pre;
     ca.part = part;
