@@ -51,6 +51,16 @@ void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64
                     hipStream_t stream) {
   const char* bank = static_cast<const char*>(d_bank);
   const int32_t* members = reinterpret_cast<const int32_t*>(bank + p.off_members);
+  // launch limits of every group before any launch, so an error queues nothing
+  for (int32_t gi = g_begin; gi < g_end; ++gi) {
+    const Group& g = p.groups[gi];
+    int32_t lo, hi;
+    member_range(g, t_begin, t_end, &lo, &hi);
+    if (lo >= hi || g.path != JERK_PATH_FFT_FP32) continue;
+    const int64_t U = g.seg_len - g.taps + 1;
+    const int64_t tiles = (nbins + U - 1) / U * ((hi - lo + g.tpb - 1) / g.tpb);
+    require(tiles < (1ll << 31), JERK_EINVAL, "search too large for one launch; split the template range");
+  }
   for (int32_t gi = g_begin; gi < g_end; ++gi) {
     const Group& g = p.groups[gi];
     int32_t lo, hi;

@@ -249,3 +249,17 @@ def test_plain_c_caller_is_built():
     assert os.path.exists(demo), "tests/c_abi/jerk_demo is missing: build the library first"
     r = subprocess.run([demo], capture_output=True, text=True, timeout=60)
     assert r.returncode == 1 and "usage" in r.stderr
+
+
+def test_oversized_search_is_refused_before_anything_is_queued():
+    """A spectrum so long that a width group's FFT tiles exceed one launch: EINVAL from the
+    host-side check, before any group is queued (no device call is made here)."""
+    import ctypes as C
+    from paper_1911_01353_amd import _lib
+    lib = _lib.load()
+    one = C.c_void_p(8)
+    plan = J.Plan(4096, 200.0, 600.0, 2.0, 20.0, path="fft")
+    T = plan.info()["n_templates"]
+    n = 1 << 36
+    assert lib.jerk_search(plan.handle, one, one, n, one, 2 * n, 0, T, None, 0, None) == _lib.JERK_EINVAL
+    assert "too large" in lib.jerk_last_error().decode()
