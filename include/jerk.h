@@ -222,6 +222,18 @@ typedef struct jerk_peak {
   uint32_t p;
 } jerk_peak;
 
+/* Per-row peaks of rows [t_begin, t_end) without writing the plane: d_out[t - t_begin] holds the
+ * largest power of row t and its plane index p (the lowest p among equal powers), what a row
+ * argmax of jerk_search's plane gives, on any path (the FFT and MFMA epilogues keep one key per
+ * row). d_ws: device workspace of jerk_search_peaks_workspace_bytes bytes (8 per row), 8-byte
+ * aligned. Enqueues kernels only (no memset), so the call may be captured in a graph.
+ * EINVAL for a bad range, nbins outside [1, 2^31), NULL or misaligned pointers; ENOMEM for a
+ * short workspace. Asynchronous on stream. */
+size_t jerk_search_peaks_workspace_bytes(const jerk_plan* plan, int32_t t_begin, int32_t t_end);
+int32_t jerk_search_peaks(const jerk_plan* plan, const void* d_bank, const void* d_spec, int64_t nbins,
+                          int32_t t_begin, int32_t t_end, jerk_peak* d_out, void* d_ws, size_t ws_bytes,
+                          hipStream_t stream);
+
 /* Reduces peak keys [rows][keys_ld] (first keys_per_row of each row) to one jerk_peak per row.
  * Rows whose keys were all left 0 report power 0 and p = 0xFFFFFFFF. Asynchronous on stream. */
 int32_t jerk_peaks_reduce(const uint64_t* d_keys, int32_t rows, int64_t keys_per_row, int64_t keys_ld,

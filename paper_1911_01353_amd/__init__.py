@@ -18,7 +18,7 @@ from ._lib import (JERK_EAGAIN, JERK_ECANCELED, JERK_EHIP, JERK_EINVAL, JERK_ENO
 
 __all__ = [
     "Plan", "Server", "peaks_reduce", "stream_check", "stats_workspace_bytes", "plane_stats", "find_candidates",
-    "candidates_numpy", "CANDIDATE_DTYPE", "spectrum_workspace_bytes", "prepare_spectrum", "JERK_EHIP", "JERK_ECANCELED", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
+    "candidates_numpy", "CANDIDATE_DTYPE", "peaks_numpy", "PEAK_DTYPE", "spectrum_workspace_bytes", "prepare_spectrum", "JERK_EHIP", "JERK_ECANCELED", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
     "PATH_AUTO", "PATH_NAMES", "JERK_OK", "JERK_EINVAL", "JERK_ENOMEM", "JERK_EAGAIN", "JERK_EPENDING",
 ]
 
@@ -213,6 +213,29 @@ class Plan:
         _lib.check(_lib.load().jerk_harmonic_shape(self.handle, n_r, n_harm, C.byref(zf), C.byref(wf), C.byref(pf)))
         return zf.value, wf.value, pf.value
 
+    def search_peaks(self, bank, spec, t_begin: int = 0, t_end: int | None = None, out=None, ws=None,
+                     stream=None):
+        """Enqueue ``jerk_search_peaks``: per-row peaks of rows [t_begin, t_end) without a plane.
+        Returns ``out``, a (rows, 2) int32 device tensor of jerk_peak records (float32 power bits,
+        uint32 p); ``peaks_numpy`` turns it into a structured array."""
+        import torch
+        if spec.dtype != torch.complex64 or spec.dim() != 1 or not spec.is_contiguous():
+            raise ValueError("spec must be a contiguous 1-D complex64 tensor")
+        if t_end is None:
+            t_end = self.info()["n_templates"]
+        rows = t_end - t_begin
+        if out is None:
+            out = torch.empty((max(rows, 1), 2), dtype=torch.int32, device=spec.device)
+        if out.shape[0] < rows or out.shape[1] != 2 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous (rows, 2) tensor")
+        need = int(_lib.load().jerk_search_peaks_workspace_bytes(self.handle, t_begin, t_end))
+        if ws is None:
+            ws = torch.empty(max(need, 8), dtype=torch.uint8, device=spec.device)
+        _lib.check(_lib.load().jerk_search_peaks(self.handle, _dev_ptr(bank), _dev_ptr(spec), spec.shape[0], t_begin,
+                                                 t_end, _dev_ptr(out), _dev_ptr(ws), ws.numel() * ws.element_size(),
+                                                 _stream_ptr(stream)))
+        return out
+
     def search_candidates_workspace_bytes(self, nbins: int, pre_level: float, t_begin: int = 0,
                                           t_end: int | None = None, staged: int = 0) -> int:
         if t_end is None:
@@ -351,6 +374,15 @@ def find_candidates(plane, stats, k_sigma: float, out, count, n_r: int | None = 
     _lib.check(_lib.load().jerk_find_candidates(_dev_ptr(plane), plane.stride(0), rows, n_r, _dev_ptr(stats),
                                                 float(k_sigma), rt, t_base, _dev_ptr(out), out.shape[0],
                                                 _dev_ptr(count), _stream_ptr(stream)))
+
+
+PEAK_DTYPE = np.dtype([("power", np.float32), ("p", np.uint32)])
+
+
+def peaks_numpy(out, rows: int | None = None) -> np.ndarray:
+    """Host copy of (rows, 2) jerk_peak records as a structured array (fields power, p)."""
+    n = out.shape[0] if rows is None else rows
+    return out[:n].cpu().numpy().view(PEAK_DTYPE).reshape(n)
 
 
 def candidates_numpy(out, count) -> np.ndarray:

@@ -39,6 +39,8 @@ int32_t guarded(F&& f) {
 }
 
 void gen_twiddles(float2* out, int32_t n, hipStream_t stream);
+// reduce.hip: n copies of v (a kernel, so that the call may be captured in a graph)
+void fill_u64(uint64_t* dst, int64_t n, uint64_t v, hipStream_t stream);
 
 // Member sub-range [lo, hi) of group g whose templates lie in [t_begin, t_end).
 static void member_range(const Group& g, int32_t t_begin, int32_t t_end, int32_t* lo, int32_t* hi) {
@@ -46,9 +48,11 @@ static void member_range(const Group& g, int32_t t_begin, int32_t t_end, int32_t
   *hi = (int32_t)(std::lower_bound(g.members.begin(), g.members.end(), t_end) - g.members.begin());
 }
 
+// Plane rows [t_begin, t_end) of groups [g_begin, g_end) into d_plane and/or, when row_max is
+// set, one peak key per row (row t - t_begin, combined with atomicMax; cleared by the caller).
 void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64_t nbins, float* d_plane,
                     int64_t ld, int32_t t_begin, int32_t t_end, int32_t g_begin, int32_t g_end,
-                    hipStream_t stream) {
+                    hipStream_t stream, uint64_t* row_max = nullptr) {
   const char* bank = static_cast<const char*>(d_bank);
   const int32_t* members = reinterpret_cast<const int32_t*>(bank + p.off_members);
   // launch limits of every group before any launch, so an error queues nothing
@@ -79,6 +83,8 @@ void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64
       j.ld = ld;
       j.taps = g.taps;
       j.tpb = g.tpb;
+      j.row_max = row_max;
+      j.rmax_ld = 0;
       fft_correlate_launch(j, g.seg_len, g.ept, reinterpret_cast<const float2*>(bank + p.off_tw[tw_slot(g.seg_len)]),
                            stream);
     } else {
@@ -95,6 +101,7 @@ void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64
       a.ld = ld;
       a.taps = g.taps;
       a.path = g.path;
+      a.row_max = row_max;
       gemm_correlate_launch(a, stream);
     }
   }
@@ -443,6 +450,33 @@ int32_t jerk_find_candidates(const float* d_plane, int64_t ld, int32_t rows, int
             "t_base must be >= 0 and t_base + rows - 1 must fit int32");
     jerk::find_candidates(d_plane, ld, rows, n_r, d_stats, k_sigma, d_row_template, t_base, d_out, capacity,
                           d_count, stream);
+  });
+}
+
+size_t jerk_search_peaks_workspace_bytes(const jerk_plan* plan, int32_t t_begin, int32_t t_end) {
+  if (!plan || t_begin < 0 || t_end < t_begin || t_end > plan->p.T) return 0;
+  return (size_t)(t_end - t_begin) * sizeof(uint64_t);
+}
+
+int32_t jerk_search_peaks(const jerk_plan* plan, const void* d_bank, const void* d_spec, int64_t nbins,
+                          int32_t t_begin, int32_t t_end, jerk_peak* d_out, void* d_ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  return guarded([&] {
+    require(plan != nullptr, JERK_EINVAL, "plan must not be NULL");
+    const jerk::Plan& p = plan->p;
+    require(0 <= t_begin && t_begin <= t_end && t_end <= p.T, JERK_EINVAL, "template range outside [0, n_templates]");
+    if (t_begin == t_end) return;
+    require(d_bank && d_spec && d_out && d_ws, JERK_EINVAL, "bank, spectrum, output and workspace must not be NULL");
+    require(nbins >= 1 && nbins < (int64_t(1) << 31), JERK_EINVAL, "nbins must be in [1, 2^31)");
+    require(reinterpret_cast<uintptr_t>(d_spec) % 8 == 0 && reinterpret_cast<uintptr_t>(d_ws) % 8 == 0, JERK_EINVAL,
+            "spectrum and workspace must be 8-byte aligned");
+    const int32_t rows = t_end - t_begin;
+    require(ws_bytes >= (size_t)rows * sizeof(uint64_t), JERK_ENOMEM, "peak workspace too small");
+    uint64_t* keys = static_cast<uint64_t*>(d_ws);
+    jerk::fill_u64(keys, rows, 0ull, stream);
+    jerk::search_enqueue(p, d_bank, d_spec, nbins, nullptr, 2 * nbins, t_begin, t_end, 0, (int32_t)p.groups.size(),
+                         stream, keys);
+    jerk::peaks_reduce(keys, rows, 1, 1, d_out, stream);
   });
 }
 

@@ -1,6 +1,8 @@
 // Peak keys -> per-row peaks. A key is (float bits of a power << 32) |
 // (0xFFFFFFFF - p); the largest key of a row is its largest power, ties going
 // to the lowest plane index p.
+#include <algorithm>
+
 #include "jerk_internal.h"
 
 namespace jerk {
@@ -33,7 +35,18 @@ __global__ void peaks_reduce_kernel(const uint64_t* __restrict__ keys, int32_t r
   }
 }
 
+__global__ void fill_u64_kernel(uint64_t* __restrict__ dst, int64_t n, uint64_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = v;
+}
+
 }  // namespace
+
+void fill_u64(uint64_t* dst, int64_t n, uint64_t v, hipStream_t stream) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, dst, n, v);
+  JERK_HIP_CHECK(hipGetLastError());
+}
 
 void peaks_reduce(const uint64_t* keys, int32_t rows, int64_t per_row, int64_t ld, jerk_peak* out,
                   hipStream_t stream) {

@@ -263,3 +263,21 @@ def test_oversized_search_is_refused_before_anything_is_queued():
     n = 1 << 36
     assert lib.jerk_search(plan.handle, one, one, n, one, 2 * n, 0, T, None, 0, None) == _lib.JERK_EINVAL
     assert "too large" in lib.jerk_last_error().decode()
+
+
+def test_search_peaks_validates_on_the_host():
+    import ctypes as C
+    from paper_1911_01353_amd import _lib
+    lib = _lib.load()
+    one = C.c_void_p(8)
+    plan = J.Plan(4096, 20.0, 60.0, 2.0, 20.0, path="auto")
+    T = plan.info()["n_templates"]
+    assert lib.jerk_search_peaks_workspace_bytes(plan.handle, 0, T) == 8 * T
+    assert lib.jerk_search_peaks_workspace_bytes(plan.handle, 0, T + 1) == 0
+    f = lib.jerk_search_peaks
+    assert f(plan.handle, None, None, 4096, 3, 3, None, None, 0, None) == _lib.JERK_OK
+    assert f(None, one, one, 4096, 0, T, one, one, 8 * T, None) == _lib.JERK_EINVAL
+    assert f(plan.handle, one, one, 0, 0, T, one, one, 8 * T, None) == _lib.JERK_EINVAL
+    assert f(plan.handle, one, one, 4096, 0, T, None, one, 8 * T, None) == _lib.JERK_EINVAL
+    assert f(plan.handle, one, C.c_void_p(12), 4096, 0, T, one, one, 8 * T, None) == _lib.JERK_EINVAL
+    assert f(plan.handle, one, one, 4096, 0, T, one, one, 8 * T - 1, None) == _lib.JERK_ENOMEM

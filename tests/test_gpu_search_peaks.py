@@ -1,0 +1,82 @@
+"""Per-row peaks without a plane (jerk_search_peaks) against the row maximum and its index in the
+plane that jerk_search writes for the same plan and spectrum: power bit-equal, index equal (the
+lowest index among equal powers on both sides), on every path, for a ragged spectrum length, a
+template slab, and inside a replayed graph."""
+
+import numpy as np
+import pytest
+
+import paper_1911_01353_amd as J
+
+from gpu_helpers import build_bank, device, gpu_plane
+
+pytestmark = pytest.mark.gpu
+
+
+def _spectrum(n, seed):
+    rng = np.random.default_rng(seed)
+    x = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) / np.sqrt(2)
+    x[n // 3] += 8.0
+    return x.astype(np.complex64)
+
+
+def _row_peaks(plane):
+    idx = np.argmax(plane, axis=1)  # first index of the largest value
+    return plane[np.arange(plane.shape[0]), idx], idx
+
+
+@pytest.mark.parametrize("path", ["fft", "split_bf16", "fp16", "auto"])
+def test_peaks_equal_plane_row_maxima(path):
+    import torch
+    dev = device()
+    n = 20011
+    plan = J.Plan(n, 20.0, 60.0, 2.0, 20.0, path=path)
+    bank = build_bank(plan)
+    spec_np = _spectrum(n, 3)
+    T = plan.info()["n_templates"]
+    plane = gpu_plane(plan, bank, spec_np)
+    wp, wi = _row_peaks(plane)
+    spec = torch.from_numpy(spec_np).to(dev)
+    for t0, t1 in ((0, T), (13, 101)):
+        out = plan.search_peaks(bank, spec, t0, t1)
+        torch.cuda.synchronize()
+        got = J.peaks_numpy(out, t1 - t0)
+        assert np.array_equal(got["power"].view(np.uint32), wp[t0:t1].view(np.uint32)), path
+        assert np.array_equal(got["p"].astype(np.int64), wi[t0:t1]), path
+    plan.close()
+
+
+def test_peaks_graph_replays():
+    import torch
+    dev = device()
+    n = 8192
+    plan = J.Plan(n, 20.0, 60.0, 2.0, 20.0, path="auto")
+    bank = build_bank(plan)
+    T = plan.info()["n_templates"]
+    a, b = _spectrum(n, 4), _spectrum(n, 5)
+    spec = torch.from_numpy(a).to(dev)
+    out = torch.empty((T, 2), dtype=torch.int32, device=dev)
+    ws = torch.empty(8 * T, dtype=torch.uint8, device=dev)
+    want = {}
+    for key, x in (("a", a), ("b", b)):
+        spec.copy_(torch.from_numpy(x).to(dev))
+        plan.search_peaks(bank, spec, out=out, ws=ws)
+        torch.cuda.synchronize()
+        want[key] = J.peaks_numpy(out).copy()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.search_peaks(bank, spec, out=out, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.search_peaks(bank, spec, out=out, ws=ws)
+    for rep, key in enumerate(("a", "b", "a", "b")):
+        spec.copy_(torch.from_numpy(a if key == "a" else b).to(dev))
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(J.peaks_numpy(out), want[key]), rep
+    plan.close()
