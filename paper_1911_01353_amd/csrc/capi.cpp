@@ -41,6 +41,9 @@ int32_t guarded(F&& f) {
 void gen_twiddles(float2* out, int32_t n, hipStream_t stream);
 // reduce.hip: n copies of v (a kernel, so that the call may be captured in a graph)
 void fill_u64(uint64_t* dst, int64_t n, uint64_t v, hipStream_t stream);
+// gemm_correlate.hip: several narrow MFMA-path groups in one launch (up to 8 jobs)
+bool gemm_multi_eligible(const GemmArgs& a);
+void gemm_correlate_multi_launch(const GemmArgs* jobs, int n, hipStream_t stream);
 
 // Member sub-range [lo, hi) of group g whose templates lie in [t_begin, t_end).
 static void member_range(const Group& g, int32_t t_begin, int32_t t_end, int32_t* lo, int32_t* hi) {
@@ -65,6 +68,14 @@ void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64
     const int64_t tiles = (nbins + U - 1) / U * ((hi - lo + g.tpb - 1) / g.tpb);
     require(tiles < (1ll << 31), JERK_EINVAL, "search too large for one launch; split the template range");
   }
+  // narrow MFMA-path groups of one kind (split-BF16 or FP16) go out together in one launch
+  GemmArgs pending[8];
+  int n_pending = 0;
+  auto flush = [&]() {
+    if (n_pending == 1) gemm_correlate_launch(pending[0], stream);
+    else if (n_pending > 1) gemm_correlate_multi_launch(pending, n_pending, stream);
+    n_pending = 0;
+  };
   for (int32_t gi = g_begin; gi < g_end; ++gi) {
     const Group& g = p.groups[gi];
     int32_t lo, hi;
@@ -102,9 +113,16 @@ void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64
       a.taps = g.taps;
       a.path = g.path;
       a.row_max = row_max;
-      gemm_correlate_launch(a, stream);
+      if (gemm_multi_eligible(a)) {
+        if (n_pending > 0 && pending[0].path != a.path) flush();
+        pending[n_pending++] = a;
+        if (n_pending == 8) flush();
+      } else {
+        gemm_correlate_launch(a, stream);
+      }
     }
   }
+  flush();
 }
 
 // Rows [m_begin, m_end) of group g's member list, output row = member - m_begin.

@@ -21,6 +21,8 @@
 // Yr phase 1, Yi phase 1). In the 32x32 accumulator, lane l holds column l%32
 // and, in registers 4q..4q+3, the four components of template 2q + l/32, so
 // each lane forms both phases' powers in place and stores them as one float2.
+#include <algorithm>
+
 #include "jerk_internal.h"
 
 namespace jerk {
@@ -60,8 +62,8 @@ __host__ __device__ constexpr int window_cols() { return 32 * CT; }
 // to KC k-steps stay in registers; the spectrum window is double-buffered in
 // LDS and the next window's loads are issued before the current window's MFMAs.
 template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT, bool KEYS, int KT>
-__global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64_t windows_per_wg, int64_t n_colchunks) {
-  extern __shared__ uint32_t lds32[];
+__device__ __forceinline__ void gemm_tile(const GemmArgs& a, int64_t windows_per_wg, int64_t n_colchunks, int64_t blk,
+                                          uint32_t* lds32) {
   constexpr int P = SPLIT ? 2 : 1;        // parts of each operand (hi, lo)
   constexpr int NPART = 2 * P;            // LDS part arrays (re/im x hi/lo)
   constexpr int COLS = window_cols<CT>();
@@ -72,8 +74,8 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
   const int WW = win_words(COLS, K);
   const int buf_words = NPART * 2 * WW;
   const int lane = threadIdx.x;
-  const int64_t cc = blockIdx.x % n_colchunks;
-  const int tblk = (int)(blockIdx.x / n_colchunks);
+  const int64_t cc = blk % n_colchunks;
+  const int tblk = (int)(blk / n_colchunks);
   const int n_members = a.m_end - a.m_begin;
   const int rb0 = a.m_begin / 8 + tblk * RB;  // first row block (group-relative)
   const uint16_t* __restrict__ frag = static_cast<const uint16_t*>(a.bank_gemm);
@@ -387,6 +389,45 @@ __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64
   }
 }
 
+template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT, bool KEYS, int KT>
+__global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64_t windows_per_wg, int64_t n_colchunks) {
+  extern __shared__ uint32_t lds32[];
+  gemm_tile<RB, CT, KC, MAXLD, SPLIT, RESIDENT, KEYS, KT>(a, windows_per_wg, n_colchunks, blockIdx.x, lds32);
+}
+
+// Several narrow width groups in one launch (split-BF16 with at most 64 taps, or FP16 with
+// at most 256): workgroup i belongs to the job whose block range holds it and runs that
+// job's kernel body (one per tap count), so a small search is one launch instead of one per
+// group. The job table travels in the kernel arguments.
+constexpr int kGemmMultiJobs = 8;
+struct GemmMulti {
+  GemmArgs job[kGemmMultiJobs];
+  int64_t windows_per_wg[kGemmMultiJobs];
+  int64_t n_colchunks[kGemmMultiJobs];
+  int64_t block_begin[kGemmMultiJobs + 1];
+  int32_t n;
+};
+
+template <bool SPLIT, bool KEYS>
+__global__ void __launch_bounds__(64, 2) gemm_multi_kernel(GemmMulti m) {
+  extern __shared__ uint32_t lds32[];
+  const int64_t blk = blockIdx.x;
+  int j = 0;
+  while (j + 1 < m.n && blk >= m.block_begin[j + 1]) ++j;
+  const GemmArgs& a = m.job[j];
+  const int64_t local = blk - m.block_begin[j];
+  if constexpr (SPLIT) {
+    switch (a.taps) {
+      case 16: gemm_tile<1, 4, 4, 4, true, true, KEYS, 16>(a, m.windows_per_wg[j], m.n_colchunks[j], local, lds32); break;
+      case 32: gemm_tile<1, 4, 4, 4, true, true, KEYS, 32>(a, m.windows_per_wg[j], m.n_colchunks[j], local, lds32); break;
+      case 48: gemm_tile<1, 4, 8, 4, true, true, KEYS, 48>(a, m.windows_per_wg[j], m.n_colchunks[j], local, lds32); break;
+      default: gemm_tile<1, 4, 8, 4, true, true, KEYS, 64>(a, m.windows_per_wg[j], m.n_colchunks[j], local, lds32); break;
+    }
+  } else {
+    gemm_tile<1, 2, 32, 6, false, true, KEYS, 0>(a, m.windows_per_wg[j], m.n_colchunks[j], local, lds32);
+  }
+}
+
 // Converts FP64 taps [n][2][K] into tap-operand fragments [rb][ks][part][lane][8].
 __global__ void gemm_frag_kernel(const double2* __restrict__ taps, uint16_t* __restrict__ out, int n, int K,
                                  int split, int64_t total) {
@@ -456,18 +497,29 @@ void gemm_bank_build(const Plan& p, const Group& g, const double2* taps, void* o
 
 namespace {
 
+struct GemmGrid {
+  int64_t windows_per_wg, n_colchunks, blocks;
+};
+
+// Workgroups of one job: RB row blocks of 8 templates each by runs of consecutive windows of
+// 32 CT outputs, about 4096 workgroups (4 waves' worth per CU slot) or fewer.
+GemmGrid gemm_grid(const GemmArgs& a, int RB, int CT) {
+  const int n_members = a.m_end - a.m_begin;
+  const int cols = 32 * CT;
+  const int64_t n_win = (a.nbins + cols - 1) / cols;
+  const int64_t n_tblk = (n_members + 8 * RB - 1) / (8 * RB);
+  int64_t wpw = 1;
+  while (n_tblk * ((n_win + wpw - 1) / wpw) > 4096 && wpw < 256) wpw *= 2;
+  const int64_t ncc = (n_win + wpw - 1) / wpw;
+  return {wpw, ncc, n_tblk * ncc};
+}
+
 template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT, bool KEYS, int KT = 0>
 void launch_cfg(const GemmArgs& a, hipStream_t stream) {
   require(KT == 0 || a.taps == KT, JERK_EINTERNAL, "GEMM kernel built for another tap count");
-  const int n_members = a.m_end - a.m_begin;
   constexpr int COLS = window_cols<CT>();
-  const int64_t n_win = (a.nbins + COLS - 1) / COLS;
-  const int64_t n_tblk = (n_members + 8 * RB - 1) / (8 * RB);
-  // about 4 waves' worth of workgroups per CU slot; each walks consecutive windows
-  int64_t windows_per_wg = 1;
-  while (n_tblk * ((n_win + windows_per_wg - 1) / windows_per_wg) > 4096 && windows_per_wg < 256) windows_per_wg *= 2;
-  const int64_t n_colchunks = (n_win + windows_per_wg - 1) / windows_per_wg;
-  const int64_t blocks = n_tblk * n_colchunks;
+  const GemmGrid gg = gemm_grid(a, RB, CT);
+  const int64_t windows_per_wg = gg.windows_per_wg, n_colchunks = gg.n_colchunks, blocks = gg.blocks;
   require(blocks < (1ll << 31), JERK_EINVAL, "search too large for one launch");
   require(COLS + a.taps + 8 <= 64 * MAXLD, JERK_EINTERNAL, "GEMM window larger than the per-lane load budget");
   require(!RESIDENT || 2 * a.taps / 16 <= KC, JERK_EINTERNAL, "resident tap fragments exceed the register budget");
@@ -516,6 +568,47 @@ void launch_split_resident(const GemmArgs& a, hipStream_t stream) {
     case 112: launch_cfg<1, 2, 16, 4, true, true, KEYS, 112>(a, stream); break;
     default: launch_cfg<1, 2, 16, 4, true, true, KEYS, 128>(a, stream); break;
   }
+}
+
+bool gemm_multi_eligible(const GemmArgs& a) {
+  return a.path == JERK_PATH_GEMM_FP16 ? a.taps <= 256 : a.taps <= 64;
+}
+
+// One launch for jobs[0..n) (2 <= n <= 8), all eligible, all split-BF16 or all FP16, all with
+// or all without peak keys, each m_begin a multiple of 8.
+void gemm_correlate_multi_launch(const GemmArgs* jobs, int n, hipStream_t stream) {
+  require(n >= 1 && n <= kGemmMultiJobs, JERK_EINTERNAL, "bad GEMM job count");
+  const bool split = jobs[0].path != JERK_PATH_GEMM_FP16;
+  const bool keys = jobs[0].row_max != nullptr;
+  GemmMulti m{};
+  m.n = n;
+  size_t lds = 0;
+  int64_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    const GemmArgs& a = jobs[i];
+    require((a.path != JERK_PATH_GEMM_FP16) == split && (a.row_max != nullptr) == keys && gemm_multi_eligible(a),
+            JERK_EINTERNAL, "GEMM jobs of one launch must share path and key mode");
+    require(a.m_begin % 8 == 0 && a.taps % 16 == 0 && a.taps >= 16, JERK_EINTERNAL, "bad GEMM job");
+    const int ct = split ? 4 : 2;
+    const GemmGrid gg = gemm_grid(a, 1, ct);
+    m.job[i] = a;
+    m.windows_per_wg[i] = gg.windows_per_wg;
+    m.n_colchunks[i] = gg.n_colchunks;
+    m.block_begin[i] = total;
+    total += a.m_end > a.m_begin && a.nbins > 0 ? gg.blocks : 0;
+    lds = std::max(lds, (size_t)2 * (split ? 4 : 2) * 2 * win_words(32 * ct, a.taps) * sizeof(uint32_t));
+  }
+  m.block_begin[n] = total;
+  if (total == 0) return;
+  require(total < (1ll << 31), JERK_EINVAL, "search too large for one launch");
+  if (split) {
+    if (keys) hipLaunchKernelGGL((gemm_multi_kernel<true, true>), dim3((unsigned)total), dim3(64), lds, stream, m);
+    else hipLaunchKernelGGL((gemm_multi_kernel<true, false>), dim3((unsigned)total), dim3(64), lds, stream, m);
+  } else {
+    if (keys) hipLaunchKernelGGL((gemm_multi_kernel<false, true>), dim3((unsigned)total), dim3(64), lds, stream, m);
+    else hipLaunchKernelGGL((gemm_multi_kernel<false, false>), dim3((unsigned)total), dim3(64), lds, stream, m);
+  }
+  JERK_HIP_CHECK(hipGetLastError());
 }
 
 void gemm_correlate_launch(const GemmArgs& a, hipStream_t stream) {
