@@ -112,7 +112,20 @@ CandLayout cand_layout(const Plan& p, int64_t nbins, int32_t t_begin, int32_t t_
   L.slab = L.pool + align_up((size_t)L.pool_cap * sizeof(CandPoolHit));
   L.slab_stats = L.slab + align_up((size_t)max_slab * (size_t)L.slab_ld * sizeof(float));
   L.slab_ws = L.slab_stats + align_up((size_t)max_slab * 2 * sizeof(double));
-  L.total = L.slab_ws + align_up(max_slab > 0 ? stats_workspace_bytes((int32_t)max_slab, 2 * nbins) : 0);
+  // statistics workspace for every slab size used: full slabs and each group's last one
+  // (the size is not monotonic in the row count)
+  size_t stats_ws = 0;
+  if (max_slab > 0) {
+    stats_ws = stats_workspace_bytes((int32_t)max_slab, 2 * nbins);
+    for (const Group& g : p.groups) {
+      int32_t lo, hi;
+      group_range(g, t_begin, t_end, &lo, &hi);
+      if (lo >= hi || g.path == JERK_PATH_FFT_FP32) continue;
+      const int32_t last = (hi - lo) % (int32_t)max_slab;
+      if (last > 0) stats_ws = std::max(stats_ws, stats_workspace_bytes(last, 2 * nbins));
+    }
+  }
+  L.total = L.slab_ws + align_up(stats_ws);
   return L;
 }
 

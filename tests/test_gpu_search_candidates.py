@@ -257,19 +257,21 @@ def test_short_workspace():
     assert ei.value.status == J.JERK_ENOMEM
 
 
-def test_full_size_sampled_rows():
+@pytest.mark.parametrize("path", ["fft", "auto"])
+def test_full_size_sampled_rows(path):
     """The 2^22-bin search (12261 templates, zmax 200, wmax 600) with fused selection in the bench's
-    configuration (autotuned FFT plan, k = 6, speculative level 6.3), checked on whole rows: two
-    corners, the centre and the templates nearest two injected tones. Each row's candidates and
-    statistics against the library's two-step path on that row (exact bar) and against the FP64
-    oracle's row (every disagreement at a decision within the plane's error)."""
+    configuration (autotuned plan, k = 6, speculative level 6.3), checked on whole rows: two
+    corners, the centre, the templates nearest two injected tones and (AUTO: on the split-BF16
+    path, through plane slabs whose last one is partial) rows of the 48- and 64-tap groups. Each
+    row's candidates and statistics against the library's two-step path on that row (exact bar)
+    and against the FP64 oracle's row (every disagreement at a decision within the plane's error)."""
     import torch
     dev = device()
     cfg = synth.CONFIGS["bins2e22_z200_w600"]
     spec_np = synth.make_spectrum(cfg)
     n = spec_np.shape[0]
     spec = torch.from_numpy(spec_np).to(dev)
-    plan = J.Plan(n, cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path="fft")
+    plan = J.Plan(n, cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
     plan.autotune(spec)
     bank = build_bank(plan)
     T = plan.info()["n_templates"]
@@ -289,7 +291,7 @@ def test_full_size_sampled_rows():
         i = int(round((zb + cfg.zmax) / cfg.dz))
         j = int(round(w / cfg.dw)) + J_w
         tone_rows.append(j * n_z + i)
-    rows = [0, T - 1, T // 2] + tone_rows
+    rows = [0, T - 1, T // 2] + tone_rows + [J_w * n_z + 105, J_w * n_z + 115]  # zbar 10, 30 at w 0: 42, 62 taps
     sel = out[:total][torch.isin(out[:total, 0], torch.tensor(rows, dtype=torch.int32, device=dev))]
     got_all = np.sort(sel.cpu().numpy().view(J.CANDIDATE_DTYPE).reshape(-1), order=["t", "p"])
     st_all = stats.cpu().numpy()
