@@ -240,3 +240,33 @@ def test_widest_templates_zmax300(path):
         ora = _wide_oracle(spec, grid, ts)
         assert error_summary(got, ora)["max"] <= TOL[path], (g, gi["taps"])
     plan.close()
+
+
+@pytest.mark.parametrize("path", ["fft", "split_bf16", "fp16"])
+def test_max_length_widest_templates(path):
+    """The largest case of the serving workload: 2^23 bins (2^24 outputs per row) on the
+    zmax 300, wmax 900 grid, two rows of its widest width group, against the oracle on windows
+    at both ends and in the middle of the rows."""
+    import torch
+    dev = device()
+    rng = np.random.default_rng(823)
+    n = 1 << 23
+    spec = ((rng.standard_normal(n) + 1j * rng.standard_normal(n)) / np.sqrt(2)).astype(np.complex64)
+    grid = Grid(300.0, 900.0, 2.0, 20.0)
+    plan = J.Plan(n, 300.0, 900.0, 2.0, 20.0, path=path)
+    bank = build_bank(plan)
+    groups = plan.groups()
+    members = plan.members()
+    g = len(groups) - 1
+    gi = groups[g]
+    m = min(2, gi["n_members"])
+    slab = torch.full((m, 2 * n), float("nan"), dtype=torch.float32, device=dev)
+    plan.search_members(bank, torch.from_numpy(spec).to(dev), slab, g, 0, m)
+    torch.cuda.synchronize()
+    got = slab.cpu().numpy()
+    assert not np.isnan(got).any()
+    ts = [int(t) for t in members[gi["first_member"]: gi["first_member"] + m]]
+    for lo, hi in ((0, 4096), (n - 2048, n + 2048), (2 * n - 4096, 2 * n)):
+        ora = oracle_plane(spec, grid, templates=ts, p_lo=lo, p_hi=hi)
+        assert error_summary(got[:, lo:hi], ora)["max"] <= TOL[path], (path, gi["taps"], lo)
+    plan.close()
