@@ -293,6 +293,9 @@ __device__ __forceinline__ void cand_epilogue(const CandArgs& ca, const FftJob& 
   for (int c = 0; c < E; ++c) {
     const int e = (c % M) * R1 + c / M;
     const float a = P0[e], b = P1[e];
+    // Wave-uniform: most columns of a wave hold no point above the level (about four in five at
+    // the usual level), and they need no neighbours.
+    if (__ballot(fmaxf(a, b) > thr_f) == 0ull) continue;
     const float left = dpp_f32<0x138>(fill_left(c), b);   // lane i reads P1 of lane i - 1
     const float right = dpp_f32<0x130>(fill_right(c), a);  // lane i reads P0 of lane i + 1
     const int lag = tid + TPB * c;
