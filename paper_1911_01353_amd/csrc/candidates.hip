@@ -442,37 +442,36 @@ __global__ void __launch_bounds__(256) cand_filter_kernel(const CandHit* __restr
 
 // The first and last point of every (row, segment), whose neighbours lie in the
 // adjacent segments. edge[2 i] = (P0, P1) at lag 0, edge[2 i + 1] = (P0, P1) at
-// the last lag, i = row n_seg + segment.
+// the last lag, i = row n_seg + segment. Grid (segment blocks, rows).
 __global__ void __launch_bounds__(256) cand_edges_kernel(const float2* __restrict__ edge, int32_t rows, int64_t n_seg,
                                                          int32_t U, int64_t nbins, const CandRowStat* __restrict__ rs,
                                                          const int32_t* __restrict__ members,
                                                          jerk_candidate* __restrict__ out, int64_t capacity,
                                                          unsigned long long* __restrict__ count) {
-  const int64_t total = (int64_t)rows * n_seg;
-  for (int64_t base = (int64_t)blockIdx.x * 256; base < total; base += (int64_t)gridDim.x * 256) {
-    const int64_t i = base + threadIdx.x;
-    bool h0 = false, h1 = false;
-    float a0 = 0.0f, b1 = 0.0f;
-    uint32_t t = 0u, p0 = 0u, p1 = 0u;
-    CandRowStat st{0.0, 0.0, 0.0, 0, 0};
-    if (i < total) {
-      const int32_t r = (int32_t)(i / n_seg);
-      const int64_t sg = i % n_seg;
-      const float2 first = edge[2 * i], last = edge[2 * i + 1];
-      st = rs[r];
-      t = (uint32_t)members[r];
-      const int64_t lim = nbins - sg * U < U ? nbins - sg * U : U;
-      a0 = first.x;
-      b1 = last.y;
-      p0 = (uint32_t)(2 * (sg * U));
-      p1 = (uint32_t)(2 * (sg * U + lim - 1) + 1);
-      const bool left_ok = sg == 0 || a0 > edge[2 * (i - 1) + 1].y;
-      h0 = left_ok && a0 >= first.y && (double)a0 > st.thr;
-      const bool right_ok = sg + 1 == n_seg || b1 >= edge[2 * (i + 1)].x;
-      h1 = b1 > last.x && right_ok && (double)b1 > st.thr;
+  for (int32_t r = blockIdx.y; r < rows; r += gridDim.y) {
+    const CandRowStat st = rs[r];
+    const uint32_t t = (uint32_t)members[r];
+    const float2* row_edge = edge + 2 * (int64_t)r * n_seg;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n_seg; base += (int64_t)gridDim.x * 256) {
+      const int64_t sg = base + threadIdx.x;
+      bool h0 = false, h1 = false;
+      float a0 = 0.0f, b1 = 0.0f;
+      uint32_t p0 = 0u, p1 = 0u;
+      if (sg < n_seg) {
+        const float2 first = row_edge[2 * sg], last = row_edge[2 * sg + 1];
+        const int64_t lim = nbins - sg * U < U ? nbins - sg * U : U;
+        a0 = first.x;
+        b1 = last.y;
+        p0 = (uint32_t)(2 * (sg * U));
+        p1 = (uint32_t)(2 * (sg * U + lim - 1) + 1);
+        const bool left_ok = sg == 0 || a0 > row_edge[2 * (sg - 1) + 1].y;
+        h0 = left_ok && a0 >= first.y && (double)a0 > st.thr;
+        const bool right_ok = sg + 1 == n_seg || b1 >= row_edge[2 * (sg + 1)].x;
+        h1 = b1 > last.x && right_ok && (double)b1 > st.thr;
+      }
+      emit_candidates(h0, t, p0, a0, st.mean, st.sigma, out, capacity, count);
+      emit_candidates(h1, t, p1, b1, st.mean, st.sigma, out, capacity, count);
     }
-    emit_candidates(h0, t, p0, a0, st.mean, st.sigma, out, capacity, count);
-    emit_candidates(h1, t, p1, b1, st.mean, st.sigma, out, capacity, count);
   }
 }
 
@@ -526,11 +525,11 @@ void cand_filter(const CandHit* hits, const uint32_t* tile_hits, int32_t tiles, 
 void cand_edges(const float2* edge, int32_t rows, int64_t n_seg, int32_t U, int64_t nbins, const CandRowStat* rs,
                 const int32_t* d_members, jerk_candidate* out, int64_t capacity, unsigned long long* count,
                 hipStream_t stream) {
-  const int64_t total = (int64_t)rows * n_seg;
-  if (total <= 0) return;
-  const int64_t blocks = std::min<int64_t>(4096, (total + 255) / 256);
-  hipLaunchKernelGGL(cand_edges_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, edge, rows, n_seg, U, nbins,
-                     rs, d_members, out, capacity, count);
+  if (rows <= 0 || n_seg <= 0) return;
+  const int64_t bx = std::min<int64_t>(64, (n_seg + 255) / 256);
+  const dim3 grid((unsigned)bx, (unsigned)(rows < kMaxGridY ? rows : kMaxGridY));
+  hipLaunchKernelGGL(cand_edges_kernel, grid, dim3(256), 0, stream, edge, rows, n_seg, U, nbins, rs, d_members, out,
+                     capacity, count);
   JERK_HIP_CHECK(hipGetLastError());
 }
 
