@@ -243,15 +243,18 @@ class Plan:
         return int(_lib.load().jerk_search_candidates_workspace_bytes(self.handle, nbins, t_begin, t_end,
                                                                       float(pre_level), staged))
 
-    def search_candidates(self, bank, spec, k_sigma: float, pre_level: float, out, count, t_begin: int = 0,
+    def search_candidates(self, bank, spec, k_sigma: float, pre_level: float | None, out, count, t_begin: int = 0,
                           t_end: int | None = None, staged: int = 0, stats=None, ws=None, stream=None):
         """Enqueue ``jerk_search_candidates``: the search of rows [t_begin, t_end) with candidate
-        selection and no plane. ``out``: (capacity, 4) int32 device tensor of jerk_candidate records;
-        ``count``: one-element int64 device tensor the caller zeroes first; ``staged``: staging slots
-        per tile (0 = automatic); ``stats``: optional (rows, 2) float64 device tensor of row (mean,
-        sigma). ``ws`` is allocated here when omitted; returns it so that the caller can keep it
-        alive with the stream."""
+        selection and no plane. ``pre_level``: the speculative level (None: 0.9 (1 + k_sigma), for a
+        spectrum of unit mean power); ``out``: (capacity, 4) int32 device tensor of jerk_candidate
+        records; ``count``: one-element int64 device tensor the caller zeroes first; ``staged``:
+        staging slots per tile (0 = automatic); ``stats``: optional (rows, 2) float64 device tensor
+        of row (mean, sigma). ``ws`` is allocated here when omitted; returns it so that the caller
+        can keep it alive with the stream."""
         import torch
+        if pre_level is None:
+            pre_level = 0.9 * (1.0 + float(k_sigma))
         if spec.dtype != torch.complex64 or spec.dim() != 1 or not spec.is_contiguous():
             raise ValueError("spec must be a contiguous 1-D complex64 tensor")
         if out.dim() != 2 or out.shape[1] != 4 or not out.is_contiguous():
