@@ -648,7 +648,7 @@ def serving_leg(J, torch, n_req, load):
                         "wmax 3 zmax, dz 2, dw 20, 50% tones, 50% split-BF16; peaks mode"}
 
 
-def batch_leg(J, torch, n_items, slab_rows=128):
+def batch_leg(J, torch, n_items, slab_rows=128, cand_items=32):
     """256 uneven de-dispersion-trial spectra (2^20, 2^21, 2^22 bins; zmax 100, wmax 300) through
     jerk_batch_search: one graph-replayed persistent launch per template slab over all spectra.
     Spectra are N(0,1) noise generated on the GPU (seeded torch generator) and normalised to unit
@@ -693,9 +693,32 @@ def batch_leg(J, torch, n_items, slab_rows=128):
     torch.cuda.synchronize()
     wall_flat = time.perf_counter() - t0
     seg = plan.group(0)["seg_len"]
+    # candidates of the first cand_items spectra (k = 6) through jerk_batch_search_candidates: no planes
+    cands = None
+    if cand_items > 0:
+        sub = specs[:cand_items]
+        k = 6.0
+        cl = []
+        for s_ in sub:
+            cap = int(1.2e-3 * 2 * s_.shape[0] * T) + 4096
+            cl.append((s_, torch.empty((cap, 4), dtype=torch.int32, device="cuda"),
+                       torch.zeros(1, dtype=torch.int64, device="cuda"), None))
+        cws = plan.batch_search_candidates(bank, cl, k)  # warm-up; allocates the shared workspace
+        torch.cuda.synchronize()
+        for c in cl:
+            c[2].zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.batch_search_candidates(bank, cl, k, ws=cws)
+        torch.cuda.synchronize()
+        wall_c = time.perf_counter() - t0
+        pts_c = sum(2 * s_.shape[0] for s_ in sub) * T
+        cands = {"items": len(sub), "k_sigma": k, "points": pts_c, "wall_s": wall_c, "points_per_s": pts_c / wall_c,
+                 "candidates": int(sum(int(c[2].item()) for c in cl))}
+        del cl, cws
     plan.close()
     return {"items": n_items, "templates": T, "points": pts, "wall_s": wall, "points_per_s": pts / wall,
-            "flat_wall_s": wall_flat, "flat_points_per_s": pts / wall_flat,
+            "flat_wall_s": wall_flat, "flat_points_per_s": pts / wall_flat, "candidates_no_plane": cands,
             "seg_len": seg, "autotune_s": t_tune, "launches": -(-T // slab_rows),
             "workload": "synth.batch_spectra_specs(256, seed 191103) lengths; GPU noise spectra; zmax 100, wmax 300"}
 
@@ -832,7 +855,10 @@ def main():
     if args.batch_items > 0:
         batch = batch_leg(J, torch, args.batch_items)
         print(f"[bench] batch {batch['points_per_s']:.3e} points/s (persistent), "
-              f"{batch['flat_points_per_s']:.3e} (flat)", file=sys.stderr, flush=True)
+              f"{batch['flat_points_per_s']:.3e} (flat)"
+              + (f", with candidates {batch['candidates_no_plane']['points_per_s']:.3e} "
+                 f"({batch['candidates_no_plane']['items']} spectra)" if batch['candidates_no_plane'] else ""),
+              file=sys.stderr, flush=True)
     cpu = cpu_baseline(spec_np, args.cpu_templates) if args.cpu_templates > 0 else None
     cpu_fft = None
     if args.cpu_templates > 0:

@@ -350,6 +350,26 @@ int32_t jerk_search_candidates(const jerk_plan* plan, const void* d_bank, const 
                                double* d_stats, jerk_candidate* d_out, int64_t capacity,
                                unsigned long long* d_count, void* d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* Many spectra (e.g. de-dispersion trials) through jerk_search_candidates in one call, one after
+ * the other on the stream, sharing one workspace; each item has its own candidate list. Every item
+ * is checked before anything is queued. d_ws: at least jerk_batch_search_candidates_workspace_bytes
+ * (the largest single-search workspace over the items). Asynchronous on stream. */
+typedef struct jerk_batch_cand_item {
+  const void* spec;            /* device complex64 spectrum [nbins]                               */
+  int64_t nbins;               /* in [1, 2^31)                                                    */
+  jerk_candidate* out;         /* device candidate list of this spectrum                          */
+  int64_t capacity;            /* records out holds                                               */
+  unsigned long long* count;   /* device count of this spectrum's candidates; cleared by the caller */
+  double* stats;               /* device (mean, sigma) per row [t_end - t_begin][2], or NULL       */
+} jerk_batch_cand_item;
+
+size_t jerk_batch_search_candidates_workspace_bytes(const jerk_plan* plan, const jerk_batch_cand_item* items,
+                                                    int32_t count, int32_t t_begin, int32_t t_end, double pre_level,
+                                                    int64_t staged);
+int32_t jerk_batch_search_candidates(const jerk_plan* plan, const void* d_bank, const jerk_batch_cand_item* items,
+                                     int32_t count, int32_t t_begin, int32_t t_end, double k_sigma, double pre_level,
+                                     int64_t staged, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- serving: continuous batching of search requests ----------------------- */
 typedef struct jerk_server jerk_server;
 

@@ -236,6 +236,38 @@ class Plan:
                                                  _stream_ptr(stream)))
         return out
 
+    def batch_search_candidates(self, bank, items, k_sigma: float, pre_level: float | None = None,
+                                t_begin: int = 0, t_end: int | None = None, staged: int = 0, ws=None, stream=None):
+        """Enqueue ``jerk_batch_search_candidates`` over ``items``: (spec, out, count, stats or None)
+        per spectrum, as for ``search_candidates``. Returns the workspace (allocated when omitted)."""
+        import torch
+        if pre_level is None:
+            pre_level = 0.9 * (1.0 + float(k_sigma))
+        if t_end is None:
+            t_end = self.info()["n_templates"]
+        arr = (_lib.BatchCandItem * max(1, len(items)))()
+        for i, (spec, out, count, stats) in enumerate(items):
+            if spec.dtype != torch.complex64 or spec.dim() != 1 or not spec.is_contiguous():
+                raise ValueError("spec must be a contiguous 1-D complex64 tensor")
+            if out.dim() != 2 or out.shape[1] != 4 or not out.is_contiguous():
+                raise ValueError("out must be a contiguous (capacity, 4) tensor")
+            arr[i].spec = _dev_ptr(spec).value
+            arr[i].nbins = spec.shape[0]
+            arr[i].out = _dev_ptr(out).value
+            arr[i].capacity = out.shape[0]
+            arr[i].count = _dev_ptr(count).value
+            arr[i].stats = _dev_ptr(stats).value if stats is not None else None
+        lib = _lib.load()
+        if ws is None:
+            need = int(lib.jerk_batch_search_candidates_workspace_bytes(self.handle, arr, len(items), t_begin, t_end,
+                                                                        float(pre_level), staged))
+            dev = items[0][0].device if items else "cuda"
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        _lib.check(lib.jerk_batch_search_candidates(self.handle, _dev_ptr(bank), arr, len(items), t_begin, t_end,
+                                                    float(k_sigma), float(pre_level), staged, _dev_ptr(ws),
+                                                    ws.numel() * ws.element_size(), _stream_ptr(stream)))
+        return ws
+
     def search_candidates_workspace_bytes(self, nbins: int, pre_level: float, t_begin: int = 0,
                                           t_end: int | None = None, staged: int = 0) -> int:
         if t_end is None:

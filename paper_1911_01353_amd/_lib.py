@@ -66,6 +66,13 @@ class BatchItem(C.Structure):
     ]
 
 
+class BatchCandItem(C.Structure):
+    _fields_ = [
+        ("spec", C.c_void_p), ("nbins", C.c_int64), ("out", C.c_void_p), ("capacity", C.c_int64),
+        ("count", C.c_void_p), ("stats", C.c_void_p),
+    ]
+
+
 class Peak(C.Structure):
     _fields_ = [("power", C.c_float), ("p", C.c_uint32)]
 
@@ -142,6 +149,11 @@ SIGNATURES = {
                                      C.c_size_t, C.c_void_p]),
     "jerk_find_candidates": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_void_p, C.c_double,
                                          C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "jerk_batch_search_candidates_workspace_bytes": (C.c_size_t, [C.c_void_p, C.POINTER(BatchCandItem), C.c_int32,
+                                                                  C.c_int32, C.c_int32, C.c_double, C.c_int64]),
+    "jerk_batch_search_candidates": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(BatchCandItem), C.c_int32, C.c_int32,
+                                                  C.c_int32, C.c_double, C.c_double, C.c_int64, C.c_void_p, C.c_size_t,
+                                                  C.c_void_p]),
     "jerk_search_peaks_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int32, C.c_int32]),
     "jerk_search_peaks": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
                                       C.c_void_p, C.c_size_t, C.c_void_p]),

@@ -41,6 +41,12 @@ int32_t guarded(F&& f) {
 void gen_twiddles(float2* out, int32_t n, hipStream_t stream);
 // reduce.hip: n copies of v (a kernel, so that the call may be captured in a graph)
 void fill_u64(uint64_t* dst, int64_t n, uint64_t v, hipStream_t stream);
+// search_candidates.cpp: many spectra through the search with candidate selection
+size_t batch_search_candidates_workspace_bytes(const Plan& p, const jerk_batch_cand_item* items, int32_t count,
+                                               int32_t t_begin, int32_t t_end, double pre, int64_t staged);
+void batch_search_candidates(const Plan& p, const void* d_bank, const jerk_batch_cand_item* items, int32_t count,
+                             int32_t t_begin, int32_t t_end, double k_sigma, double pre, int64_t staged, void* d_ws,
+                             size_t ws_bytes, hipStream_t stream);
 // gemm_correlate.hip: several narrow MFMA-path groups in one launch (up to 8 jobs)
 bool gemm_multi_eligible(const GemmArgs& a);
 void gemm_correlate_multi_launch(const GemmArgs* jobs, int n, hipStream_t stream);
@@ -495,6 +501,39 @@ int32_t jerk_search_peaks(const jerk_plan* plan, const void* d_bank, const void*
     jerk::search_enqueue(p, d_bank, d_spec, nbins, nullptr, 2 * nbins, t_begin, t_end, 0, (int32_t)p.groups.size(),
                          stream, keys);
     jerk::peaks_reduce(keys, rows, 1, 1, d_out, stream);
+  });
+}
+
+size_t jerk_batch_search_candidates_workspace_bytes(const jerk_plan* plan, const jerk_batch_cand_item* items,
+                                                    int32_t count, int32_t t_begin, int32_t t_end, double pre_level,
+                                                    int64_t staged) {
+  if (!plan || (!items && count > 0) || count < 0 || staged < 0 || !std::isfinite(pre_level) || t_begin < 0 ||
+      t_end < t_begin || t_end > plan->p.T)
+    return 0;
+  for (int32_t i = 0; i < count; ++i)
+    if (items[i].nbins < 1 || items[i].nbins >= (int64_t(1) << 31)) return 0;
+  return jerk::batch_search_candidates_workspace_bytes(plan->p, items, count, t_begin, t_end, pre_level, staged);
+}
+
+int32_t jerk_batch_search_candidates(const jerk_plan* plan, const void* d_bank, const jerk_batch_cand_item* items,
+                                     int32_t count, int32_t t_begin, int32_t t_end, double k_sigma, double pre_level,
+                                     int64_t staged, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    require(plan != nullptr, JERK_EINVAL, "plan must not be NULL");
+    require(count >= 0 && (items || count == 0), JERK_EINVAL, "items must not be NULL when count > 0");
+    require(t_begin >= 0 && t_begin <= t_end && t_end <= plan->p.T, JERK_EINVAL, "bad template range");
+    require(std::isfinite(k_sigma) && std::isfinite(pre_level), JERK_EINVAL, "k_sigma and pre_level must be finite");
+    require(staged >= 0, JERK_EINVAL, "staged must be >= 0");
+    if (count == 0 || t_begin == t_end) return;
+    require(d_bank && d_ws, JERK_EINVAL, "bank and workspace must not be NULL");
+    for (int32_t i = 0; i < count; ++i) {
+      const jerk_batch_cand_item& it = items[i];
+      require(it.nbins >= 1 && it.nbins < (int64_t(1) << 31), JERK_EINVAL, "item nbins must be in [1, 2^31)");
+      require(it.spec && it.count && it.capacity >= 0 && (it.out || it.capacity == 0), JERK_EINVAL,
+              "item spectrum, count and (with capacity > 0) output must not be NULL");
+    }
+    jerk::batch_search_candidates(plan->p, d_bank, items, count, t_begin, t_end, k_sigma, pre_level, staged, d_ws,
+                                  ws_bytes, stream);
   });
 }
 

@@ -136,11 +136,9 @@ size_t search_candidates_workspace_bytes(const Plan& p, int64_t nbins, int32_t t
   return cand_layout(p, nbins, t_begin, t_end, pre, staged).total;
 }
 
-void search_candidates(const Plan& p, const void* d_bank, const void* d_spec, int64_t nbins, int32_t t_begin,
-                       int32_t t_end, double k_sigma, double pre, double* d_stats, jerk_candidate* d_out,
-                       int64_t capacity, unsigned long long* d_count, int64_t staged, void* d_ws, size_t ws_bytes,
-                       hipStream_t stream) {
-  // every check before anything is queued
+// Every check of one search before anything of it is queued.
+void search_candidates_check(const Plan& p, int64_t nbins, int32_t t_begin, int32_t t_end, double pre, int64_t staged,
+                             size_t ws_bytes) {
   for (const Group& g : p.groups) {
     int32_t lo, hi;
     group_range(g, t_begin, t_end, &lo, &hi);
@@ -150,8 +148,16 @@ void search_candidates(const Plan& p, const void* d_bank, const void* d_spec, in
     require(group_tiles(g, hi - lo, nbins) < (int64_t(1) << 31) && group_segments(g, nbins) < (int64_t(1) << 31),
             JERK_EINVAL, "search too large for one launch; split the template range");
   }
+  require(ws_bytes >= cand_layout(p, nbins, t_begin, t_end, pre, staged).total, JERK_ENOMEM,
+          "search-candidates workspace too small");
+}
+
+void search_candidates(const Plan& p, const void* d_bank, const void* d_spec, int64_t nbins, int32_t t_begin,
+                       int32_t t_end, double k_sigma, double pre, double* d_stats, jerk_candidate* d_out,
+                       int64_t capacity, unsigned long long* d_count, int64_t staged, void* d_ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  search_candidates_check(p, nbins, t_begin, t_end, pre, staged, ws_bytes);
   const CandLayout L = cand_layout(p, nbins, t_begin, t_end, pre, staged);
-  require(ws_bytes >= L.total, JERK_ENOMEM, "search-candidates workspace too small");
   char* ws = static_cast<char*>(d_ws);
   double2* part = reinterpret_cast<double2*>(ws + L.part);
   float2* edge = reinterpret_cast<float2*>(ws + L.edge);
@@ -230,6 +236,28 @@ void search_candidates(const Plan& p, const void* d_bank, const void* d_spec, in
                 row_t, d_out, capacity, d_count, stream);
     cand_edges(edge, rows, n_seg, U, nbins, rs, row_t, d_out, capacity, d_count, stream);
     fft_cand_launch(j, g.seg_len, g.ept, tw, ca, 2, stream);
+  }
+}
+
+// Many spectra, one after the other on the stream in one workspace (each search's steps
+// finish reading the workspace before the next search's first step writes it: stream order).
+size_t batch_search_candidates_workspace_bytes(const Plan& p, const jerk_batch_cand_item* items, int32_t count,
+                                               int32_t t_begin, int32_t t_end, double pre, int64_t staged) {
+  size_t most = 0;
+  for (int32_t i = 0; i < count; ++i)
+    most = std::max(most, cand_layout(p, items[i].nbins, t_begin, t_end, pre, staged).total);
+  return most;
+}
+
+void batch_search_candidates(const Plan& p, const void* d_bank, const jerk_batch_cand_item* items, int32_t count,
+                             int32_t t_begin, int32_t t_end, double k_sigma, double pre, int64_t staged, void* d_ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  for (int32_t i = 0; i < count; ++i)
+    search_candidates_check(p, items[i].nbins, t_begin, t_end, pre, staged, ws_bytes);
+  for (int32_t i = 0; i < count; ++i) {
+    const jerk_batch_cand_item& it = items[i];
+    search_candidates(p, d_bank, it.spec, it.nbins, t_begin, t_end, k_sigma, pre, it.stats, it.out, it.capacity,
+                      it.count, staged, d_ws, ws_bytes, stream);
   }
 }
 

@@ -281,3 +281,30 @@ def test_search_peaks_validates_on_the_host():
     assert f(plan.handle, one, one, 4096, 0, T, None, one, 8 * T, None) == _lib.JERK_EINVAL
     assert f(plan.handle, one, C.c_void_p(12), 4096, 0, T, one, one, 8 * T, None) == _lib.JERK_EINVAL
     assert f(plan.handle, one, one, 4096, 0, T, one, one, 8 * T - 1, None) == _lib.JERK_ENOMEM
+
+
+def test_batch_search_candidates_validates_on_the_host():
+    import ctypes as C
+    from paper_1911_01353_amd import _lib
+    lib = _lib.load()
+    plan = J.Plan(4096, 20.0, 60.0, 2.0, 20.0, path="fft")
+    T = plan.info()["n_templates"]
+    items = (_lib.BatchCandItem * 2)()
+    for i, n in enumerate((4096, 1 << 16)):
+        items[i].spec, items[i].nbins, items[i].out, items[i].capacity, items[i].count = 8, n, 8, 10, 8
+    one = lib.jerk_search_candidates_workspace_bytes(plan.handle, 1 << 16, 0, T, 2.7, 0)
+    assert lib.jerk_batch_search_candidates_workspace_bytes(plan.handle, items, 2, 0, T, 2.7, 0) == one
+    f = lib.jerk_batch_search_candidates
+    ws = C.c_void_p(8)
+    assert f(plan.handle, ws, items, 0, 0, T, 2.0, 2.7, 0, ws, 0, None) == _lib.JERK_OK
+    assert f(None, ws, items, 2, 0, T, 2.0, 2.7, 0, ws, one, None) == _lib.JERK_EINVAL
+    assert f(plan.handle, ws, None, 2, 0, T, 2.0, 2.7, 0, ws, one, None) == _lib.JERK_EINVAL
+    items[1].nbins = 0
+    assert f(plan.handle, ws, items, 2, 0, T, 2.0, 2.7, 0, ws, one, None) == _lib.JERK_EINVAL
+    items[1].nbins = 1 << 16
+    items[1].count = None
+    assert f(plan.handle, ws, items, 2, 0, T, 2.0, 2.7, 0, ws, one, None) == _lib.JERK_EINVAL
+    items[1].count = 8
+    # the second item needs more than the first: a workspace sized for the first is refused up front
+    small = lib.jerk_search_candidates_workspace_bytes(plan.handle, 4096, 0, T, 2.7, 0)
+    assert f(plan.handle, ws, items, 2, 0, T, 2.0, 2.7, 0, ws, small, None) == _lib.JERK_ENOMEM

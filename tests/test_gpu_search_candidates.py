@@ -351,3 +351,31 @@ def test_zero_spectrum_and_negative_k(fft_plan):
         st, got, _ = _fused(plan, bank, spec, k, pre, staged)
         _same(got, want, plane, stats, k)
     assert len(want) > plane.size // 8
+
+
+def test_batch_equals_single_searches():
+    """Spectra of different lengths through one batched call (one shared workspace) give, per
+    spectrum, the candidates and statistics of the single-spectrum call."""
+    import torch
+    dev = device()
+    plan = J.Plan(1 << 15, 20.0, 60.0, 2.0, 20.0, path="auto")
+    bank = build_bank(plan)
+    T = plan.info()["n_templates"]
+    lengths = [30011, 1 << 15, 777, 12345]
+    k = 2.0
+    items, want = [], []
+    for i, n in enumerate(lengths):
+        x = _spectrum(n, 300 + i, tone=(n // 2, 9.0))
+        st, got, c = _fused(plan, bank, x, k, 0.9 * (1 + k))
+        want.append((st, got, c))
+        spec = torch.from_numpy(x).to(dev)
+        out = torch.zeros((max(64, T * n), 4), dtype=torch.int32, device=dev)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+        stats = torch.empty((T, 2), dtype=torch.float64, device=dev)
+        items.append((spec, out, cnt, stats))
+    plan.batch_search_candidates(bank, items, k)
+    torch.cuda.synchronize()
+    for (spec, out, cnt, stats), (st, got, c) in zip(items, want):
+        assert int(cnt.item()) == c
+        assert np.array_equal(J.candidates_numpy(out, cnt), got)
+        assert np.array_equal(stats.cpu().numpy(), st)
