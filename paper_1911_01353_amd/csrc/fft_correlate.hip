@@ -36,6 +36,21 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
 }
 
+// Global-memory views for a job's pointers. A pointer read from a device-side
+// job table (batched launches) may point anywhere as far as the compiler knows,
+// so it emits flat accesses: 64-bit per-lane addresses, and waits that also
+// cover LDS traffic. Through these views the accesses stay global loads and
+// stores. Kernels that take the job as a kernel argument need no view (the
+// compiler knows such pointers are global).
+typedef float f2vec __attribute__((ext_vector_type(2)));
+using gcf2_ptr = __attribute__((address_space(1))) const f2vec*;
+using gf2_ptr = __attribute__((address_space(1))) f2vec*;
+using gci32_ptr = __attribute__((address_space(1))) const int32_t*;
+__device__ __forceinline__ float2 gload(gcf2_ptr p) {
+  const f2vec q = *p;
+  return make_float2(q.x, q.y);
+}
+
 // cos / sin of 2 pi m / 16, m = 0..7
 __device__ constexpr float kC16[8] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
                                       0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f};
@@ -386,8 +401,9 @@ __device__ __forceinline__ void cand_epilogue(const CandArgs& ca, const FftJob& 
 // list. CAND = 0 writes the plane rows and/or the per-(row, segment) peak
 // keys; CAND = 1 and 2 write neither and run the candidate epilogue instead
 // (cand_epilogue). Radices R1..R4 (R4 = 1: three passes) run forward in that
-// order and inverse in the reverse order.
-template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS, int CAND = 0>
+// order and inverse in the reverse order. TABLE: the job was read from a
+// device-side job table (its accesses go through the global views).
+template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS, int CAND = 0, bool TABLE = false>
 __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, int m1, float2* lds, uint64_t* red,
                                          const float2* __restrict__ tw, const CandArgs* ca = nullptr,
                                          float* xch = nullptr, double2* wsum = nullptr, uint32_t* n_hit = nullptr) {
@@ -409,7 +425,7 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, i
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
         const int64_t k = base + b + r * (S / R1);
-        v[m * R1 + r] = (k >= 0 && k < j.nbins) ? j.spec[k] : make_float2(0.f, 0.f);
+        v[m * R1 + r] = (k >= 0 && k < j.nbins) ? (TABLE ? gload((gcf2_ptr)j.spec + k) : j.spec[k]) : make_float2(0.f, 0.f);
       }
     }
   }
@@ -429,19 +445,20 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, i
   // lags kept by this segment: lag < U and k0 = seg U + lag < nbins
   const int lag_lim = (int)min((int64_t)U, j.nbins - seg * U);
   for (int mm = m0; mm < m1; ++mm) {
-    const int t = j.members[mm];
+    const int t = TABLE ? ((gci32_ptr)j.members)[mm] : j.members[mm];
     const int64_t row = j.row_by_member ? (int64_t)(mm - j.row_base) : (int64_t)(t - j.t_begin);
     float P0[E];
 #pragma unroll
     for (int phase = 0; phase < 2; ++phase) {
       const float2* __restrict__ H = j.bank_fft + ((int64_t)mm * 2 + phase) * S;
+      const gcf2_ptr Hg = (gcf2_ptr)j.bank_fft + ((int64_t)mm * 2 + phase) * S;  // TABLE
       {
         constexpr int M = E / RL;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
           const unsigned b = tid + m * TPB;
 #pragma unroll
-          for (int k = 0; k < RL; ++k) v[m * RL + k] = cmul(F[m * RL + k], H[b + k * (S / RL)]);
+          for (int k = 0; k < RL; ++k) v[m * RL + k] = cmul(F[m * RL + k], TABLE ? gload(Hg + b + k * (S / RL)) : H[b + k * (S / RL)]);
         }
       }
       if constexpr (P4) {
@@ -470,6 +487,7 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, i
         // uniform row base; lanes add 32-bit offsets
         float2* __restrict__ out2 =
             j.plane ? reinterpret_cast<float2*>(j.plane + row * j.ld) + seg * U : nullptr;
+        const gf2_ptr out2g = j.plane ? (gf2_ptr)(j.plane + row * j.ld) + seg * U : nullptr;  // TABLE
 #pragma unroll
         for (int m = 0; m < M; ++m) {
           const int b = tid + m * TPB;
@@ -480,7 +498,10 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, i
               const float2 vv = v[m * R1 + k];
               const float p0 = P0[m * R1 + k];
               const float p1 = fmaf(vv.x, vv.x, vv.y * vv.y);
-              if (out2) out2[(unsigned)lag] = make_float2(p0, p1);
+              if (out2) {
+                if constexpr (TABLE) out2g[(unsigned)lag] = f2vec{p0, p1};
+                else out2[(unsigned)lag] = make_float2(p0, p1);
+              }
               if constexpr (KEYS) {
                 const int64_t p = 2 * (seg * U + lag);
                 const uint64_t k0 = peak_key(p0, p), k1 = peak_key(p1, p + 1);
@@ -539,15 +560,18 @@ __global__ void __launch_bounds__(S / E) fft_persistent_kernel(const FftJob* __r
       if (jobs[mid].tile_begin <= tile) lo = mid;
       else hi = mid - 1;
     }
+    lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: the job's fields go to scalar registers
     const FftJob& j = jobs[lo];
     const int64_t local = tile - j.tile_begin;
     // An opaque copy of the twiddle pointer per tile: otherwise the compiler
     // hoists the twiddle loads out of the tile loop and keeps them live across
-    // tiles, which costs more registers (and waves) than reloading them.
-    const float2* twt = tw;
-    asm volatile("" : "+s"(twt));
+    // tiles, which costs more registers (and waves) than reloading them. The
+    // copy is made in the global address space so that the loads stay global.
+    __attribute__((address_space(1))) const float2* twg = (__attribute__((address_space(1))) const float2*)tw;
+    asm volatile("" : "+s"(twg));
+    const float2* twt = (const float2*)twg;
     const int m0 = j.m_begin + (int)(local / j.n_seg) * j.tpb;
-    fft_tile<S, E, R1, R2, R3, R4, KEYS>(j, local % j.n_seg, m0, min(m0 + j.tpb, j.m_end), lds, red, twt);
+    fft_tile<S, E, R1, R2, R3, R4, KEYS, 0, true>(j, local % j.n_seg, m0, min(m0 + j.tpb, j.m_end), lds, red, twt);
   }
 }
 
@@ -567,10 +591,11 @@ __global__ void __launch_bounds__(S / E) fft_multi_kernel(const FftJob* __restri
     if (jobs[mid].tile_begin <= tile) lo = mid;
     else hi = mid - 1;
   }
+  lo = __builtin_amdgcn_readfirstlane(lo);
   const FftJob& j = jobs[lo];
   const int64_t local = tile - j.tile_begin;
   const int m0 = j.m_begin + (int)(local / j.n_seg) * j.tpb;
-  fft_tile<S, E, R1, R2, R3, R4, KEYS>(j, local % j.n_seg, m0, min(m0 + j.tpb, j.m_end), lds, red, tw);
+  fft_tile<S, E, R1, R2, R3, R4, KEYS, 0, true>(j, local % j.n_seg, m0, min(m0 + j.tpb, j.m_end), lds, red, tw);
 }
 
 // Candidate passes over one width-group job (cand_epilogue). Mode 1: one
