@@ -137,3 +137,41 @@ def test_stream_check_reports_finished_work():
     torch.cuda.synchronize()
     assert J.stream_check() == J.JERK_OK
     plan.close()
+
+
+@pytest.mark.parametrize("flat", [False, True])
+def test_batch_full_size_matches_single_searches(flat):
+    """At the batched workload's sizes (spectra of 2^20, 2^21 + 4321 and 2^22 bins; zmax 100,
+    wmax 300, 3131 templates) the batched launch writes the same bits as single searches, on the
+    narrowest and the widest 16-template slabs, and its fused row peaks are the planes' argmax."""
+    import torch
+    dev = device()
+    lengths = [1 << 20, (1 << 21) + 4321, 1 << 22]
+    plan = J.Plan(1 << 22, 100.0, 300.0, 2.0, 20.0, path="fft")
+    bank = build_bank(plan)
+    T = plan.info()["n_templates"]
+    specs_np = _spectra(lengths, 1911)
+    ws = torch.empty(plan.batch_workspace_bytes(len(specs_np)), dtype=torch.uint8, device=dev)
+    specs = [torch.from_numpy(s).to(dev) for s in specs_np]
+    for t0, t1 in ((0, 16), (T - 16, T)):
+        rows = t1 - t0
+        planes = [torch.full((rows, 2 * s.shape[0]), float("nan"), dtype=torch.float32, device=dev) for s in specs]
+        keys = [torch.zeros((rows, plan.keys_per_row(s.shape[0])), dtype=torch.int64, device=dev) for s in specs]
+        plan.batch_search(bank, list(zip(specs, planes, keys)), ws, t0, t1, graph=True, flat=flat)
+        torch.cuda.synchronize()
+        for s, pl, k in zip(specs, planes, keys):
+            n = s.shape[0]
+            ref = torch.full((rows, 2 * n), float("nan"), dtype=torch.float32, device=dev)
+            plan.search(bank, s, ref, t0, t1)
+            torch.cuda.synchronize()
+            print(f"[full-size batch] flat={flat} rows [{t0}, {t1}) nbins {n}", flush=True)
+            assert torch.equal(pl.view(torch.int32), ref.view(torch.int32)), (n, t0)
+            red = torch.empty((rows, 2), dtype=torch.int32, device=dev)
+            J.peaks_reduce(k, plan.keys_per_row(n), red)
+            torch.cuda.synchronize()
+            r = red.cpu().numpy()
+            hp, hi = _row_peaks(ref.cpu().numpy())
+            assert np.array_equal(r[:, 0].view(np.float32), hp) and np.array_equal(r[:, 1].view(np.uint32).astype(np.int64), hi), n
+            del ref
+        del planes, keys
+    plan.close()
