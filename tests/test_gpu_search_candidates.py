@@ -379,3 +379,38 @@ def test_batch_equals_single_searches():
         assert int(cnt.item()) == c
         assert np.array_equal(J.candidates_numpy(out, cnt), got)
         assert np.array_equal(stats.cpu().numpy(), st)
+
+
+def test_batch_full_size_equals_single_searches():
+    """At the batched workload's sizes (2^20, 2^21 + 4321 and 2^22 bins; zmax 100, wmax 300) the
+    batched call's candidates and statistics equal the single-spectrum call's, on the narrowest and
+    the widest 16-template slabs (k = 4: some 10^5 candidates per spectrum and slab)."""
+    import torch
+    dev = device()
+    plan = J.Plan(1 << 22, 100.0, 300.0, 2.0, 20.0, path="fft")
+    bank = build_bank(plan)
+    T = plan.info()["n_templates"]
+    lengths = [1 << 20, (1 << 21) + 4321, 1 << 22]
+    k = 4.0
+    specs_np = [_spectrum(n, 400 + i) for i, n in enumerate(lengths)]
+    for t0, t1 in ((0, 16), (T - 16, T)):
+        rows = t1 - t0
+        items, want = [], []
+        for x in specs_np:
+            n = x.shape[0]
+            cap = rows * 2 * n // 50
+            want.append(_fused(plan, bank, x, k, 0.9 * (1 + k), t_begin=t0, t_end=t1, capacity=cap))
+            items.append((torch.from_numpy(x).to(dev), torch.zeros((cap, 4), dtype=torch.int32, device=dev),
+                          torch.zeros(1, dtype=torch.int64, device=dev),
+                          torch.empty((rows, 2), dtype=torch.float64, device=dev)))
+        plan.batch_search_candidates(bank, items, k, t_begin=t0, t_end=t1)
+        torch.cuda.synchronize()
+        for (spec, out, cnt, stats), (st, got, c) in zip(items, want):
+            print(f"[full-size batch candidates] rows [{t0}, {t1}) nbins {spec.shape[0]}: {c} candidates",
+                  flush=True)
+            assert 0 < c <= out.shape[0]
+            assert int(cnt.item()) == c
+            assert np.array_equal(J.candidates_numpy(out, cnt), got)
+            assert np.array_equal(stats.cpu().numpy(), st)
+        del items
+    plan.close()
