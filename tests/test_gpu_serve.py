@@ -122,3 +122,26 @@ def test_injected_failure_spares_other_requests(server):
     server.inject_failure(1, 0)
     (t,) = _submit(server, specs, [3])
     assert server.wait(t, 120.0)["status"] == J.JERK_OK
+
+
+def test_full_size_request_equals_search_peaks(server):
+    """A 2^22-bin request (zmax 100, wmax 300: 3131 templates, 2.6e10 points, the large end of the
+    served mix) returns the per-row peaks of jerk_search_peaks with the same plan, bit for bit, and
+    its best point is the largest of them."""
+    import torch
+    n, zm, wm = 1 << 22, 100.0, 300.0
+    spec_np = _spec(n, 5, tone_bin=n // 3)
+    spec = torch.from_numpy(spec_np).cuda()
+    T = Grid(zm, wm, 2.0, 20.0).n_templates
+    t = server.submit(spec, zm, wm, path="fft", n_templates=T)
+    r = server.wait(t, 300.0)
+    assert r is not None and r["status"] == J.JERK_OK
+    plan = J.Plan(n, zm, wm, 2.0, 20.0, path="fft")
+    bank = build_bank(plan)
+    pk = J.peaks_numpy(plan.search_peaks(bank, spec))
+    print(f"[full-size request] {T} rows, best {r['best_power']:.2f} at ({r['best_t']}, {r['best_p']})", flush=True)
+    assert np.array_equal(r["peaks_power"].view(np.uint32), pk["power"].view(np.uint32))
+    assert np.array_equal(r["peaks_p"], pk["p"])
+    assert r["best_power"] == pk["power"].max()
+    assert pk["power"][r["best_t"]] == r["best_power"] and pk["p"][r["best_t"]] == r["best_p"]
+    plan.close()
