@@ -130,8 +130,9 @@ def test_single_template_grid():
         assert error_summary(got, ora)["max"] <= 1e-4
 
 
-def test_2e22_bins_sampled_windows():
-    """Full-size 2^22-bin search (201 x 61 templates): sampled rows and windows against the oracle."""
+def test_2e22_bins_sampled_rows():
+    """Full-size 2^22-bin search (201 x 61 templates): whole sampled rows (2^23 points each)
+    against the oracle's whole rows, so every point is floored at its own row's mean."""
     import torch
     device()
     cfg = synth.CONFIGS["bins2e22_z200_w600"]
@@ -141,42 +142,31 @@ def test_2e22_bins_sampled_windows():
     T = grid.n_templates
     # templates: the four corners (widest), the centre, and the one nearest each injected tone
     picks = {0, grid.n_z - 1, T - grid.n_z, T - 1, T // 2}
-    tone_windows = []
+    tone_at = []
     for tone in cfg.tones:
         rbar = tone.r0 + tone.z0 / 2 + tone.w0 / 6
         zbar = tone.z0 + tone.w0 / 2
         i = int(round((zbar + cfg.zmax) / cfg.dz))
         j = int(round(tone.w0 / cfg.dw)) + grid.J
         picks.add(j * grid.n_z + i)
-        tone_windows.append(int(2 * rbar) - 300)
-    windows = [0, n - 300, 2 * n - 600] + tone_windows
-    # oracle windows: taps once per (template, phase), direct correlation per window
-    ora = {}
-    for t in sorted(picks):
-        zb, w, h = grid.params(t)
-        taps = [template_taps(zb, w, h, ph) for ph in (0, 1)]
-        for p0 in windows:
-            k_lo, k_hi = p0 // 2, (p0 + 600 + 1) // 2
-            vals = np.zeros(600)
-            for ph in (0, 1):
-                y = correlate_row(spec, taps[ph], h, k_lo, k_hi)
-                p = 2 * np.arange(k_lo, k_hi) + ph
-                keep = (p >= p0) & (p < p0 + 600)
-                vals[p[keep] - p0] = (y.real ** 2 + y.imag ** 2)[keep]
-            ora[(t, p0)] = vals
+        tone_at.append((j * grid.n_z + i, int(round(2 * rbar))))
+    picks = sorted(picks)
+    ora = oracle_plane(spec, grid, templates=picks)
     for path in ("fft", "auto", "split_bf16", "fp16"):
         plan = J.Plan(n, cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
         bank = build_bank(plan)
-        worst = 0.0
-        for t in sorted(picks):
-            row = gpu_plane(plan, bank, spec, t, t + 1)[0]
-            assert not np.isnan(row).any()
-            for p0 in windows:
-                worst = max(worst, error_summary(row[None, p0:p0 + 600], ora[(t, p0)][None, :])["max"])
+        got = np.stack([gpu_plane(plan, bank, spec, t, t + 1)[0] for t in picks])
+        assert not np.isnan(got).any()
+        s = error_summary(got, ora)
         del bank
         torch.cuda.empty_cache()
-        print(f"2^22 bins {path}: worst sampled error {worst:.3e}")
-        assert worst <= TOL[path], (path, worst)
+        print(f"2^22 bins {path}: {len(picks)} whole rows, max {s['max']:.3e} rms {s['rms']:.3e}")
+        assert s["max"] <= TOL[path], (path, s)
+        # each tone's row peaks within a bin of the tone, at the same point as the oracle's row
+        for t, p in tone_at:
+            r = picks.index(t)
+            assert peak_index(got[r:r + 1]) == peak_index(ora[r:r + 1]), (path, t)
+            assert abs(peak_index(ora[r:r + 1])[1] - p) <= 2, (t, p)
 
 
 @pytest.mark.parametrize("path", ["fft", "split_bf16"])
@@ -242,11 +232,21 @@ def test_widest_templates_zmax300(path):
     plan.close()
 
 
+_MAXLEN_ORACLE = {}
+
+
+def _max_length_oracle(spec, grid, ts):
+    key = tuple(ts)
+    if key not in _MAXLEN_ORACLE:
+        _MAXLEN_ORACLE[key] = oracle_plane(spec, grid, templates=list(ts))
+    return _MAXLEN_ORACLE[key]
+
+
 @pytest.mark.parametrize("path", ["fft", "split_bf16", "fp16"])
 def test_max_length_widest_templates(path):
     """The largest case of the serving workload: 2^23 bins (2^24 outputs per row) on the
-    zmax 300, wmax 900 grid, two rows of its widest width group, against the oracle on windows
-    at both ends and in the middle of the rows."""
+    zmax 300, wmax 900 grid, two whole rows of its widest width group against the oracle's
+    whole rows."""
     import torch
     dev = device()
     rng = np.random.default_rng(823)
@@ -266,7 +266,42 @@ def test_max_length_widest_templates(path):
     got = slab.cpu().numpy()
     assert not np.isnan(got).any()
     ts = [int(t) for t in members[gi["first_member"]: gi["first_member"] + m]]
-    for lo, hi in ((0, 4096), (n - 2048, n + 2048), (2 * n - 4096, 2 * n)):
-        ora = oracle_plane(spec, grid, templates=ts, p_lo=lo, p_hi=hi)
-        assert error_summary(got[:, lo:hi], ora)["max"] <= TOL[path], (path, gi["taps"], lo)
+    ora = _max_length_oracle(spec, grid, ts)
+    s = error_summary(got, ora)
+    print(f"2^23 bins, {gi['taps']} taps, {path}: whole rows max {s['max']:.3e} rms {s['rms']:.3e}")
+    assert s["max"] <= TOL[path], (path, gi["taps"], s)
     plan.close()
+
+
+def test_fdas_plan_wmax0_zmax200():
+    """An FDAS plan (constant acceleration only: wmax = 0, zmax = 200; 201 templates, 32 to 232
+    taps) on a 2^18-bin spectrum with an accelerated tone: whole sampled rows against the oracle
+    on every path, and the tone found at its analytic (zbar, r)."""
+    import torch
+    device()
+    tone = synth.Tone(0.03, 70000.1, 58.1, 0.0, 0.4)
+    spec = synth.spectrum_from_series(synth.time_series(1 << 19, 191147, (tone,)))
+    n = spec.shape[0]
+    grid = Grid(200.0, 0.0, 2.0, 20.0)
+    assert grid.n_w == 1 and grid.n_templates == 201
+    t_tone = int(round((tone.z0 + 200.0) / 2.0))              # zbar = z0 when w = 0
+    p_tone = int(round(2 * (tone.r0 + tone.z0 / 2)))          # rbar = r0 + z0 / 2
+    picks = sorted({0, 1, 50, 100, 150, 199, 200, t_tone})
+    ora = oracle_plane(spec, grid, templates=picks)
+    r_tone = picks.index(t_tone)
+    assert peak_index(ora[r_tone:r_tone + 1])[1] == p_tone
+    for path in ("fft", "split_bf16", "fp16", "auto"):
+        plan = J.Plan(n, 200.0, 0.0, 2.0, 20.0, path=path)
+        info = plan.info()
+        assert (info["n_z"], info["n_w"], info["n_templates"]) == (201, 1, 201)
+        bank = build_bank(plan)
+        full = gpu_plane(plan, bank, spec)
+        assert not np.isnan(full).any()
+        got = full[picks]
+        s = error_summary(got, ora)
+        print(f"FDAS {path}: max {s['max']:.3e} rms {s['rms']:.3e}")
+        assert s["max"] <= TOL[path], (path, s)
+        assert peak_index(full) == (t_tone, p_tone), path
+        del bank, full
+        torch.cuda.empty_cache()
+        plan.close()

@@ -54,3 +54,21 @@ def test_request_stream_ranges():
     specs = synth.batch_spectra_specs(256)
     assert {s[0] // 2 for s in specs} <= {2 ** 20, 2 ** 21, 2 ** 22}
     assert 10 <= sum(1 for s in specs if s[2]) <= 45
+
+
+def test_relative_error_whole_row_floor_for_windows():
+    """A window of a row is floored at the whole row's mean, not at the window's own mean."""
+    row = np.array([1.0, 1.0, 1.0, 1.0, 0.0, 10.0, 6.0, 0.0])   # whole-row mean 2.5
+    test = row + np.array([0, 0, 0, 0, 0.5, 0, 0, 0.5])
+    win = slice(4, 8)                                           # window mean 4
+    e_row = relative_power_error(test[None, :], row[None, :])[0, win]
+    e_win = relative_power_error(test[None, win], row[None, win], floor=row.mean())[0]
+    assert np.array_equal(e_row, e_win)
+    assert np.allclose(e_win, [0.2, 0.0, 0.0, 0.2])
+    # the window's own mean would have given a looser 0.125
+    assert np.allclose(relative_power_error(test[None, win], row[None, win])[0], [0.125, 0, 0, 0.125])
+    # one floor per row
+    two = np.stack([row[win], row[win]])
+    e2 = relative_power_error(two + 0.5, two, floor=[2.5, 5.0])
+    assert np.allclose(e2[:, 0], [0.2, 0.1])
+    assert error_summary(test[None, win], row[None, win], floor=2.5)["max"] == 0.2

@@ -62,8 +62,7 @@ def test_rocfft_comparator_matches_oracle():
     """The unfused library overlap-save used as the bench's comparator computes the oracle's plane."""
     import numpy as np
     import torch
-    sys.path.insert(0, ROOT)
-    import bench
+    from paper_1911_01353_amd.comparator import overlap_save, template_spectra
     from oracle.grid import Grid
     from oracle.plane import oracle_plane
     from oracle.response import template_taps
@@ -82,8 +81,8 @@ def test_rocfft_comparator_matches_oracle():
             taps[i, ph, off: off + 2 * h] = template_taps(zb, w, h, ph)
     want = oracle_plane(x, g, templates=ts)
     for S in (256, 512):
-        spectra = bench.template_spectra(torch, torch.from_numpy(taps), S)
+        spectra = template_spectra(torch.from_numpy(taps), S)
         out = torch.empty((len(ts), 2 * n), dtype=torch.float32)
-        bench.rocfft_overlap_save(torch, torch.from_numpy(x), spectra, K, out)
+        overlap_save(torch.from_numpy(x), spectra, K, out)
         err = np.abs(out.numpy() - want) / np.maximum(want, want.mean(axis=1, keepdims=True))
         assert err.max() < 1e-4
