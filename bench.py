@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_TFLOPS = 2500.0
 MFMA_FP16_TFLOPS = 2500.0
+FP32_VECTOR_PUBLISHED_TFLOPS = 157.3
 # FP32 vector FMA without packed (dual) FP32 issue: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz.
 FP32_VECTOR_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
@@ -70,6 +71,8 @@ def parse():
                     help="time the 2^15-bin search per repetition inside a graph of this many (0 = skip)")
     ap.add_argument("--save-plan", default="", help="write the main plan's per-group configuration (JSON)")
     ap.add_argument("--load-plan", default="", help="use a saved per-group configuration instead of autotuning")
+    ap.add_argument("--copy-gib", type=float, default=4.0,
+                    help="measure achievable HBM bandwidth with a device copy and a fill of this size (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the main leg, copy a buffer of this size once (HBM counter calibration)")
     return ap.parse_args()
@@ -203,42 +206,46 @@ def time_path(J, torch, spec, n, path, steps, warmup, slab_gb, want_kernels, aut
     return out
 
 
-def rocfft_overlap_save(torch, spec, spectra, taps, out):
-    """Unfused overlap-save with library FFTs: rows of `out` (float32 [m, 2n]) from template
-    spectra [m, 2, S] of K-tap templates.
-
-    Step by step, each step a separate library call that round-trips HBM: batched forward FFT of
-    all segments, pointwise product with every template spectrum, batched inverse FFT, power,
-    overlap strip and phase interleave. Template spectra are made beforehand (untimed), as a
-    library-based search would keep them.
-    """
-    n = spec.shape[0]
-    m, _, S = spectra.shape
-    K = taps
-    U = S - K + 1
-    n_seg = -(-n // U)
-    xp = torch.zeros(K // 2 - 1 + n_seg * U + S, dtype=torch.complex64, device=spec.device)
-    xp[K // 2 - 1: K // 2 - 1 + n] = spec
-    segs = xp.unfold(0, S, U)[:n_seg]
-    f = torch.fft.fft(segs)
-    for i in range(m):
-        y = torch.fft.ifft(f[None] * spectra[i][:, None, :])[..., :U]
-        pw = (y.real * y.real + y.imag * y.imag).reshape(2, n_seg * U)[:, :n]
-        out[i].view(n, 2).copy_(pw.t())
+def kernel_table(ks):
+    return {k: {"launches": v["launches"], "time_s": v["time"], "points": v["points"],
+                "avg_launch_us": v["time"] / v["launches"] * 1e6, "points_per_s": v["points"] / v["time"],
+                "tflops": v["flops"] / v["time"] / 1e12, "hbm_GBps": v["bytes"] / v["time"] / 1e9,
+                **({"mfma_frac": v["flops"] / v["time"] / 1e12 / MFMA_BF16_TFLOPS} if v["path"] else {})}
+            for k, v in ks.items()}
 
 
-def template_spectra(torch, taps, seg_len):
-    """H[f] = sum_j c_j e^{+2 pi i f j / S}: the spectrum that turns the circular product into the
-    correlation sum over taps."""
-    m, _, K = taps.shape
-    c = torch.zeros((m, 2, seg_len), dtype=torch.complex128, device=taps.device)
-    c[..., :K] = taps
-    return torch.fft.ifft(c, norm="forward").to(torch.complex64)
+def hbm_copy_leg(torch, gib=4.0, reps=10):
+    """Achievable HBM bandwidth on this device: a device-to-device copy (read + write) and a
+    fill (write only; the plane store is write-dominated) of `gib` GiB, timed with events."""
+    nel = int(gib * (1 << 30)) // 4
+    a = torch.ones(nel, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    b.copy_(a)
+    b.fill_(2.0)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev[1].record()
+    for _ in range(reps):
+        b.fill_(3.0)
+    ev[2].record()
+    torch.cuda.synchronize()
+    t_copy = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+    t_fill = ev[1].elapsed_time(ev[2]) * 1e-3 / reps
+    by = nel * 4
+    del a, b
+    return {"bytes": by, "copy_GBps": 2 * by / t_copy / 1e9, "fill_GBps": by / t_fill / 1e9,
+            "copy_frac_of_spec": 2 * by / t_copy / 1e9 / HBM_PEAK_GBS,
+            "fill_frac_of_spec": by / t_fill / 1e9 / HBM_PEAK_GBS,
+            "what": f"torch copy_ and fill_ of a {gib:g} GiB float32 buffer, {reps} reps each, HIP events"}
 
 
 def rocfft_leg(J, torch, plan, bank, spec, n, n_groups, members):
     """The fused kernels against unfused rocFFT overlap-save on the same rows (best segment length
     of the library path from 1024..8192), with the two planes compared."""
+    from paper_1911_01353_amd.comparator import overlap_save, template_spectra
     groups = plan.groups()
     order = sorted(range(len(groups)), key=lambda g: groups[g]["taps"])
     pick = sorted({order[int(round(i * (len(order) - 1) / max(1, n_groups - 1)))] for i in range(n_groups)})
@@ -266,12 +273,12 @@ def rocfft_leg(J, torch, plan, bank, spec, n, n_groups, members):
         for S in (1024, 2048, 4096, 8192):
             if S < 2 * K:
                 continue
-            spectra = template_spectra(torch, taps, S)
-            rocfft_overlap_save(torch, spec, spectra, K, ref)
+            spectra = template_spectra(taps, S)
+            overlap_save(spec, spectra, K, ref)
             torch.cuda.synchronize()
             ev[0].record()
             for _ in range(reps):
-                rocfft_overlap_save(torch, spec, spectra, K, ref)
+                overlap_save(spec, spectra, K, ref)
             ev[1].record()
             torch.cuda.synchronize()
             t = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
@@ -440,6 +447,25 @@ def spectrum_leg(J, torch, n_samples, reps=5):
             "hbm_frac": by / t / 1e9 / HBM_PEAK_GBS}
 
 
+def harmonic_touched_bytes(plan, n_r, H):
+    """HBM bytes the harmonic sum cannot avoid: every 128-byte line of the plane that holds a
+    point some output reads, plus the output. Harmonic h reads its row at stride h, so for
+    h <= 32 every line of the span [0, h (n_pf - 1)] is touched although only 1/h of its points
+    are used; rows read by several (fundamental, h) pairs count once, at their longest span."""
+    info = plan.info()
+    n_z, n_w = info["n_z"], info["n_w"]
+    i0, Jw = n_z // 2, n_w // 2
+    n_zf, n_wf, n_pf = plan.harmonic_shape(n_r, H)
+    lines = {}
+    for row in range(n_zf * n_wf):
+        di, dj = row % n_zf - n_zf // 2, row // n_zf - n_wf // 2
+        for h in range(1, H + 1):
+            t = (Jw + h * dj) * n_z + (i0 + h * di)
+            nl = -(-(h * (n_pf - 1) + 1) * 4 // 128) if h <= 32 else n_pf
+            lines[t] = max(lines.get(t, 0), nl)
+    return sum(min(nl * 128, 4 * n_r) for nl in lines.values()) + 4 * n_pf * n_zf * n_wf
+
+
 def harmonics_leg(J, torch, spec, n, reps=5):
     """Harmonic sums of the full plane of a 147-template grid (zmax 20, wmax 60) of the 2^22-bin
     spectrum (4.9 GB), for H = 2, 4, 8; algorithmic bytes 4 (H + 1) per output point."""
@@ -461,8 +487,11 @@ def harmonics_leg(J, torch, spec, n, reps=5):
         torch.cuda.synchronize()
         t = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
         pts = out.numel()
+        touched = harmonic_touched_bytes(plan, 2 * n, H)
         res[f"H{H}"] = {"output_points": pts, "ms": t * 1e3, "points_per_s": pts / t,
-                        "GBps": 4 * (H + 1) * pts / t / 1e9, "hbm_frac": 4 * (H + 1) * pts / t / 1e9 / HBM_PEAK_GBS}
+                        "GBps": 4 * (H + 1) * pts / t / 1e9, "hbm_frac": 4 * (H + 1) * pts / t / 1e9 / HBM_PEAK_GBS,
+                        "touched_bytes": touched, "touched_GBps": touched / t / 1e9,
+                        "touched_frac": touched / t / 1e9 / HBM_PEAK_GBS}
         del out
     del plane, bank
     plan.close()
@@ -487,19 +516,41 @@ def cpu_host():
     return {"model": model, "nproc": os.cpu_count(), "affinity": avail, "workers": max(1, min(16, avail))}
 
 
+def cpu_baseline_templates(n_templates_sample):
+    """The templates whose full rows the oracle computes for cpu_baseline (evenly spaced, so
+    both ends of the lattice, the widest and the narrowest rows, are in the sample)."""
+    import numpy as np
+    T = 201 * 61
+    return [int(t) for t in np.linspace(0, T - 1, n_templates_sample)]
+
+
 def cpu_baseline(spec, n_templates_sample):
-    """The FP64 oracle, single-threaded, on full rows of a sample of templates."""
+    """The FP64 oracle, single-threaded, on full rows of a sample of templates. Returns the
+    timing record and the oracle rows (FP64), which the headline's error is measured against."""
     import numpy as np
     from oracle import Grid, oracle_plane
     grid = Grid(200.0, 600.0, 2.0, 20.0)
-    ts = [int(t) for t in np.linspace(0, grid.n_templates - 1, n_templates_sample)]
+    ts = cpu_baseline_templates(n_templates_sample)
+    assert grid.n_templates == 201 * 61
     t0 = time.perf_counter()
     plane = oracle_plane(spec, grid, templates=ts)
     dt = time.perf_counter() - t0
     pts = plane.size
     return {"value": pts / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(ts)} full rows (2^23 points each, templates {ts}) of the 2^22-bin search, "
-                      f"FP64 numpy direct correlation incl. template quadrature, {dt:.1f} s"}
+                      f"FP64 numpy direct correlation incl. template quadrature, {dt:.1f} s"}, ts, plane
+
+
+def headline_error(gpu_rows, ts, oracle_rows):
+    """Floored relative power error (whole rows, row-mean floor) of the timed plan's rows against
+    the oracle's rows of the same templates, and whether each row's peak is the oracle's."""
+    import numpy as np
+    from oracle import error_summary, peak_index
+    s = error_summary(gpu_rows, oracle_rows)
+    peaks = [peak_index(gpu_rows[i:i + 1]) == peak_index(oracle_rows[i:i + 1]) for i in range(len(ts))]
+    return {"max": s["max"], "rms": s["rms"], "row_peaks_match": bool(np.all(peaks)), "templates": ts,
+            "points": int(gpu_rows.size), "bar": 1e-4,
+            "what": "whole plane rows of the timed plan (same bank, same kernels) against the FP64 oracle's rows"}
 
 
 _POOL_SPEC = None
@@ -762,6 +813,15 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    headline_rows = None
+    if args.cpu_templates > 0:
+        rowbuf = torch.empty((1, 2 * n), dtype=torch.float32, device="cuda")
+        rows = []
+        for t in cpu_baseline_templates(args.cpu_templates):
+            main_res["plan"].search(main_res["bank"], spec, rowbuf, t, t + 1)
+            rows.append(rowbuf.cpu().numpy()[0].copy())
+        headline_rows = np.stack(rows)
+        del rowbuf
     T = main_res["T"]
     points_per_step = 2 * n * T
     wall = main_res["wall"]
@@ -769,43 +829,50 @@ def main():
     print(f"[bench] {args.path}: {value:.3e} points/s ({wall / args.steps * 1e3:.1f} ms/step)", file=sys.stderr,
           flush=True)
 
-    # dominant kernel roofline
+    # dominant kernel roofline: algorithmic bytes (4 B per plane point written + 8 B per spectrum
+    # bin read) per launch over the average launch time, against the published HBM peak
     ks = main_res["kernels"]
     dom = max(ks, key=lambda k: ks[k]["time"])
     d = ks[dom]
     avg_t = d["time"] / d["launches"]
     kernel_share = d["time"] / sum(v["time"] for v in ks.values())
+    copy = hbm_copy_leg(torch, args.copy_gib) if args.copy_gib > 0 else None
+    tflops = d["flops"] / d["launches"] / avg_t / 1e12
+    gbps = d["bytes"] / d["launches"] / avg_t / 1e9
+    roof = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBS,
+            "traffic": traffic_from_profiles(dom, d["points"] / d["launches"]),
+            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": dom, "kernel_time_share": kernel_share, "avg_launch_ms": avg_t * 1e3,
+            "launches": d["launches"], "bytes_per_launch": d["bytes"] / d["launches"],
+            "points_per_launch": d["points"] / d["launches"]}
+    if copy:
+        roof["frac_of_measured_copy"] = gbps / copy["copy_GBps"]
+        roof["frac_of_measured_fill"] = gbps / copy["fill_GBps"]
     if d["path"] == 0:
-        achieved = d["flops"] / d["launches"] / avg_t / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "peak_note": "non-packed FP32 FMA rate (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz); packed FP32 "
-                             "instructions are disabled in all device code",
-                "frac_of_packed_157_3": achieved / 157.3}
+        roof["vector_fp32"] = {
+            "achieved_tflops": tflops, "flops_counted": "nominal FFT count 5 S log2 S per transform, 6 S per "
+                                                        "spectrum product, 3 per kept lag",
+            "peak_tflops": FP32_VECTOR_PUBLISHED_TFLOPS, "frac": tflops / FP32_VECTOR_PUBLISHED_TFLOPS,
+            "nonpacked_peak_tflops": FP32_VECTOR_TFLOPS, "frac_of_nonpacked": tflops / FP32_VECTOR_TFLOPS,
+            "note": "packed FP32 instructions are disabled in all device code, so the FP32 issue ceiling is the "
+                    "non-packed rate 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz; the published 157.3 "
+                    "assumes packed FP32"}
     else:
-        achieved = d["flops"] / d["launches"] / avg_t / 1e12
-        roof = {"bound": "mfma", "achieved": achieved,
-                "peak": MFMA_BF16_TFLOPS if d["path"] == 1 else MFMA_FP16_TFLOPS, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = traffic_from_profiles(dom, d["points"] / d["launches"])
-    roof["kernel"] = dom
-    roof["kernel_time_share"] = kernel_share
-    roof["hbm_GBps"] = d["bytes"] / d["time"] / 1e9
-    roof["hbm_frac"] = roof["hbm_GBps"] / HBM_PEAK_GBS
-    roof["avg_launch_ms"] = avg_t * 1e3
-    roof["launches"] = d["launches"]
-    kernels_out = {k: {"launches": v["launches"], "time_s": v["time"], "points": v["points"],
-                       "avg_launch_us": v["time"] / v["launches"] * 1e6, "points_per_s": v["points"] / v["time"],
-                       "tflops": v["flops"] / v["time"] / 1e12, "hbm_GBps": v["bytes"] / v["time"] / 1e9}
-                   for k, v in ks.items()}
+        roof["mfma"] = {"achieved_tflops": tflops,
+                        "peak_tflops": MFMA_BF16_TFLOPS if d["path"] == 1 else MFMA_FP16_TFLOPS,
+                        "frac": tflops / (MFMA_BF16_TFLOPS if d["path"] == 1 else MFMA_FP16_TFLOPS)}
+    kernels_out = kernel_table(ks)
 
     paths = {args.path: value}
+    kernels_by_path = {}
     if args.compare_paths:
         for p in ("fft", "split_bf16"):
             if p == args.path:
                 continue
-            r = time_path(J, torch, spec, n, p, max(1, args.steps // 2), 1, args.slab_gb, False,
+            r = time_path(J, torch, spec, n, p, max(1, args.steps // 2), 1, args.slab_gb, True,
                           autotune=bool(args.autotune))
             paths[p] = points_per_step * max(1, args.steps // 2) / r["wall"]
+            kernels_by_path[p] = kernel_table(r["kernels"])
             print(f"[bench] {p}: {paths[p]:.3e} points/s", file=sys.stderr, flush=True)
             r["plan"].close()
 
@@ -859,7 +926,15 @@ def main():
               + (f", with candidates {batch['candidates_no_plane']['points_per_s']:.3e} "
                  f"({batch['candidates_no_plane']['items']} spectra)" if batch['candidates_no_plane'] else ""),
               file=sys.stderr, flush=True)
-    cpu = cpu_baseline(spec_np, args.cpu_templates) if args.cpu_templates > 0 else None
+    cpu = None
+    err_headline = None
+    if args.cpu_templates > 0:
+        cpu, ts_ora, rows_ora = cpu_baseline(spec_np, args.cpu_templates)
+        err_headline = headline_error(headline_rows, ts_ora, rows_ora)
+        print(f"[bench] headline plan against the oracle on {len(ts_ora)} whole rows: max {err_headline['max']:.2e}, "
+              f"rms {err_headline['rms']:.2e}, row peaks equal {err_headline['row_peaks_match']}",
+              file=sys.stderr, flush=True)
+        del rows_ora
     cpu_fft = None
     if args.cpu_templates > 0:
         cpu_fft = cpu_fft_overlap_save(spec_np, 16, host["workers"])
@@ -903,9 +978,12 @@ def main():
         "spectrum_preparation": prep,
         "search_2e15_bins_graph": small,
         "plane_error_2e15_bins": errors,
+        "error_vs_oracle": err_headline,
         "template_build_s": main_res["t_build"],
         "autotune_s": main_res["t_tune"],
         "kernels": kernels_out,
+        "kernels_other_paths": kernels_by_path,
+        "hbm_measured": copy,
         "serving": serving,
         "latency": latency,
         "batched_256_spectra": batch,
