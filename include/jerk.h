@@ -192,7 +192,10 @@ typedef struct jerk_batch_item {
   int64_t ld;        /* even, >= 2 nbins when plane is set                              */
   uint64_t* peaks;   /* device peak keys [t_end - t_begin][keys_ld], or NULL (see below); either
                         every item of a batch has one or none has                          */
-  int64_t keys_ld;   /* >= jerk_batch_keys_per_row(plan, nbins) when peaks is set        */
+  int64_t keys_ld;   /* >= jerk_batch_keys_per_row(plan, nbins) when peaks is set. Every
+                        key of a searched row [0, keys_ld) is written (keys past a width
+                        group's own segment count are set to 0), so the buffer needs no
+                        clearing between calls                                          */
 } jerk_batch_item;
 
 #define JERK_BATCH_GRAPH 1u /* capture the launch in a hipGraph on first use and replay it */
@@ -385,6 +388,17 @@ typedef struct jerk_serve_desc {
   int32_t reserved;
 } jerk_serve_desc;
 
+/* One entry of a request's global top-k: the k templates whose row peaks are strongest, in
+ * descending power (ties to the lower t), each with its row peak's plane index p (r = p / 2).
+ * One entry per template, so k strong templates are reported rather than k neighbouring points
+ * of one peak. */
+typedef struct jerk_top {
+  int32_t t;
+  uint32_t p;
+  float power;
+  int32_t reserved;
+} jerk_top;
+
 typedef struct jerk_request {
   const void* spec;        /* device complex64 spectrum [nbins]; caller-owned, valid until done  */
   int64_t nbins;
@@ -394,6 +408,9 @@ typedef struct jerk_request {
   float* plane;            /* optional device buffer for the plane, rows t x 2 nbins at stride ld */
   int64_t ld;
   jerk_peak* peaks;        /* optional host array: per-template peaks, filled on completion       */
+  jerk_top* top;           /* optional host array: the request's global top-k, filled on completion */
+  int32_t top_capacity;    /* k: entries of `top` (0 with top = NULL)                             */
+  int32_t reserved;
 } jerk_request;
 
 typedef struct jerk_result {
@@ -402,7 +419,7 @@ typedef struct jerk_result {
   float best_power;        /* global peak: largest power, ties to the lowest (t, p)              */
   int32_t best_t;
   uint32_t best_p;         /* r index of the peak (r = p / 2)                                    */
-  int32_t reserved;
+  int32_t top_count;       /* entries written to the request's `top` array                       */
   uint64_t points;         /* plane points searched (2 nbins x n_templates)                      */
   double t_submit, t_admit, t_first_launch, t_done; /* seconds on the server's steady clock    */
 } jerk_result;
@@ -411,6 +428,9 @@ typedef struct jerk_serve_stats {
   uint64_t submitted, completed, failed, launches, bank_builds, bank_evictions;
   int32_t queued, active;
   size_t arena_used, arena_bytes;
+  uint64_t shared_launches;  /* launches that carried work units of two or more requests           */
+  int32_t max_in_flight;     /* most requests with work on the device at one time                  */
+  int32_t reserved;
 } jerk_serve_stats;
 
 /* Creates a server whose scheduler thread runs requests on the current device. d_arena
@@ -429,7 +449,11 @@ int32_t jerk_serve_wait(jerk_server* srv, uint64_t ticket, jerk_result* out, dou
 int32_t jerk_serve_stats_get(jerk_server* srv, jerk_serve_stats* out);
 /* Test hooks: op 1 fails the n-th launch from now (counting from 1), op 2 the n-th bank build;
  * the requests involved end with JERK_EHIP and the others continue; n = 0 disarms. op 3 holds
- * admission while n != 0 (queued requests stay queued) and releases it with n = 0. */
+ * admission while n != 0 (queued requests stay queued) and releases it with n = 0. op 4 makes
+ * the next n completion queries of launch slots report a device error, as a sticky device
+ * fault would (n = 0 disarms): every request with work in flight then ends with JERK_EHIP, the
+ * slots are released and the server keeps running (later requests are served once the error
+ * clears). */
 int32_t jerk_serve_inject_failure(jerk_server* srv, int32_t op, int64_t n);
 /* Stops the scheduler after the work on the device finishes; queued requests end JERK_ECANCELED. */
 int32_t jerk_serve_destroy(jerk_server* srv);

@@ -450,8 +450,9 @@ class Server:
         self._keep = {}
 
     def submit(self, spec, zmax: float, wmax: float, dz: float = 2.0, dw: float = 20.0, path="fft", plane=None,
-               n_templates: int | None = None, nbins: int | None = None) -> int:
-        """Queue a request; returns its ticket. ``spec``: device complex64 tensor (or an address with ``nbins``)."""
+               n_templates: int | None = None, nbins: int | None = None, top_k: int = 0) -> int:
+        """Queue a request; returns its ticket. ``spec``: device complex64 tensor (or an address with ``nbins``).
+        ``n_templates``: also return every row's peak; ``top_k``: also return the k strongest row peaks."""
         if isinstance(path, str):
             path = PATH_NAMES[path]
         if isinstance(spec, int):
@@ -461,23 +462,29 @@ class Server:
         peaks = None
         if n_templates:
             peaks = (_lib.Peak * n_templates)()
+        top = (_lib.Top * top_k)() if top_k > 0 else None
         r = _lib.Request(spec=sp, nbins=n, zmax=zmax, wmax=wmax, dz=dz, dw=dw, path=path,
                          peaks_capacity=n_templates or 0,
                          plane=_dev_ptr(plane).value if plane is not None else None,
                          ld=plane.stride(0) if plane is not None else 0,
-                         peaks=C.cast(peaks, C.c_void_p) if peaks is not None else None)
+                         peaks=C.cast(peaks, C.c_void_p) if peaks is not None else None,
+                         top=C.cast(top, C.c_void_p) if top is not None else None, top_capacity=top_k)
         t = C.c_uint64()
         _lib.check(_lib.load().jerk_serve_submit(self._h, C.byref(r), C.byref(t)))
-        self._keep[t.value] = (spec, plane, peaks)
+        self._keep[t.value] = (spec, plane, peaks, top)
         return t.value
 
     def _result(self, res, ticket):
         out = {f: getattr(res, f) for f, _ in res._fields_}
-        spec, plane, peaks = self._keep.get(ticket, (None, None, None))
+        spec, plane, peaks, top = self._keep.get(ticket, (None, None, None, None))
         if peaks is not None:
             arr = np.frombuffer(peaks, dtype=np.dtype([("power", np.float32), ("p", np.uint32)])).copy()
             out["peaks_power"] = arr["power"]
             out["peaks_p"] = arr["p"]
+        if top is not None:
+            arr = np.frombuffer(top, dtype=np.dtype([("t", np.int32), ("p", np.uint32), ("power", np.float32),
+                                                     ("reserved", np.int32)]))[:res.top_count].copy()
+            out["top"] = arr[["t", "p", "power"]]
         return out
 
     def poll(self, ticket: int):

@@ -95,13 +95,18 @@ class Request(C.Structure):
         ("zmax", C.c_double), ("wmax", C.c_double), ("dz", C.c_double), ("dw", C.c_double),
         ("path", C.c_int32), ("peaks_capacity", C.c_int32),
         ("plane", C.c_void_p), ("ld", C.c_int64), ("peaks", C.c_void_p),
+        ("top", C.c_void_p), ("top_capacity", C.c_int32), ("reserved", C.c_int32),
     ]
+
+
+class Top(C.Structure):
+    _fields_ = [("t", C.c_int32), ("p", C.c_uint32), ("power", C.c_float), ("reserved", C.c_int32)]
 
 
 class Result(C.Structure):
     _fields_ = [
         ("status", C.c_int32), ("n_templates", C.c_int32), ("best_power", C.c_float), ("best_t", C.c_int32),
-        ("best_p", C.c_uint32), ("reserved", C.c_int32), ("points", C.c_uint64),
+        ("best_p", C.c_uint32), ("top_count", C.c_int32), ("points", C.c_uint64),
         ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_first_launch", C.c_double), ("t_done", C.c_double),
     ]
 
@@ -111,6 +116,7 @@ class ServeStats(C.Structure):
         ("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64), ("launches", C.c_uint64),
         ("bank_builds", C.c_uint64), ("bank_evictions", C.c_uint64), ("queued", C.c_int32), ("active", C.c_int32),
         ("arena_used", C.c_size_t), ("arena_bytes", C.c_size_t),
+        ("shared_launches", C.c_uint64), ("max_in_flight", C.c_int32), ("reserved", C.c_int32),
     ]
 
 # name -> (restype, argtypes)

@@ -517,6 +517,10 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, i
             if (j.rmax_ld == 0) atomicMax(reinterpret_cast<unsigned long long*>(j.row_max + row), (unsigned long long)best);
             else j.row_max[row * j.rmax_ld + seg] = best;
           }
+          // per-segment keys: the last segment's tile also clears the row's keys past this
+          // group's segment count, so a row holds no stale keys from an earlier spectrum
+          if (j.rmax_ld != 0 && seg == j.n_seg - 1)
+            for (int64_t q = j.n_seg + tid; q < j.rmax_ld; q += TPB) j.row_max[row * j.rmax_ld + q] = 0;
         }
       }
     }

@@ -148,6 +148,7 @@ struct jerk_server {
   std::chrono::steady_clock::time_point t0;
 
   int64_t fail_launch_at = 0, fail_build_at = 0, launch_count = 0, build_count = 0;
+  int64_t fail_queries = 0;  // completion queries still to fail (test hook)
   bool paused = false;  // admission held (test hook)
   jerk_serve_stats st{};
   size_t rr = 0;  // round-robin start
@@ -164,6 +165,15 @@ bool event_done(jerk_server& s, hipEvent_t e) {
   if (r == hipSuccess) return true;
   if (r == hipErrorNotReady) return false;
   throw Error(JERK_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(r));
+}
+
+// Completion of a launch slot; the test hook reports a device error for the next queries.
+bool slot_done(jerk_server& s, const Slot& sl) {
+  if (s.fail_queries > 0) {
+    s.fail_queries--;
+    throw Error(JERK_EHIP, "hipEventQuery: injected device error");
+  }
+  return event_done(s, sl.done);
 }
 
 void plan_for(const jerk_server& s, const jerk_request& r, Plan& p) {
@@ -249,6 +259,18 @@ void finalize(jerk_server& s, Req* q) {
       q->res.best_p = q->peaks[t].p;
     }
   if (q->r.peaks) std::memcpy(q->r.peaks, q->peaks.data(), sizeof(jerk_peak) * T);
+  if (q->r.top && !q->failed) {
+    // global top-k over the row peaks: descending power, ties to the lower template
+    std::vector<int32_t> idx((size_t)T);
+    for (int32_t t = 0; t < T; ++t) idx[t] = t;
+    const int32_t k = std::min(q->r.top_capacity, T);
+    auto before = [&](int32_t a, int32_t b) {
+      return q->peaks[a].power > q->peaks[b].power || (q->peaks[a].power == q->peaks[b].power && a < b);
+    };
+    std::partial_sort(idx.begin(), idx.begin() + k, idx.end(), before);
+    for (int32_t i = 0; i < k; ++i) q->r.top[i] = jerk_top{idx[i], q->peaks[idx[i]].p, q->peaks[idx[i]].power, 0};
+    q->res.top_count = k;
+  }
   finish(s, q);
 }
 
@@ -315,9 +337,14 @@ bool try_admit(jerk_server& s, Req* q) {
     if (inject) {
       fresh->failed = true;
     } else if (!s.dry) {
-      bank_build(fresh->plan, s.arena + boff, s.build_stream);
-      JERK_HIP_CHECK(hipEventCreateWithFlags(&fresh->ready, hipEventDisableTiming));
-      JERK_HIP_CHECK(hipEventRecord(fresh->ready, s.build_stream));
+      // a device error here fails this request (below), not the admission loop
+      try {
+        bank_build(fresh->plan, s.arena + boff, s.build_stream);
+        JERK_HIP_CHECK(hipEventCreateWithFlags(&fresh->ready, hipEventDisableTiming));
+        JERK_HIP_CHECK(hipEventRecord(fresh->ready, s.build_stream));
+      } catch (const Error&) {
+        fresh->failed = true;
+      }
     }
     b = fresh.get();
     s.banks.emplace(key, std::move(fresh));
@@ -334,9 +361,14 @@ bool try_admit(jerk_server& s, Req* q) {
     q->fail_status = JERK_EHIP;
   }
   if (!s.dry && !q->failed) {
-    JERK_HIP_CHECK(hipMemsetAsync(s.arena + mem_off, 0, (size_t)T * 8, s.build_stream));
-    JERK_HIP_CHECK(hipEventCreateWithFlags(&q->ready, hipEventDisableTiming));
-    JERK_HIP_CHECK(hipEventRecord(q->ready, s.build_stream));
+    try {
+      JERK_HIP_CHECK(hipMemsetAsync(s.arena + mem_off, 0, (size_t)T * 8, s.build_stream));
+      JERK_HIP_CHECK(hipEventCreateWithFlags(&q->ready, hipEventDisableTiming));
+      JERK_HIP_CHECK(hipEventRecord(q->ready, s.build_stream));
+    } catch (const Error& e) {
+      q->failed = true;
+      q->fail_status = e.status;
+    }
   }
   const int64_t target = std::max<int64_t>(256, s.d.tiles_per_launch / std::max(1, s.d.max_active));
   if (!q->failed) make_units(s, q, target);
@@ -404,6 +436,10 @@ bool dispatch(jerk_server& s, Slot& sl) {
   for (auto& e : taken)
     if (e.first->res.t_first_launch == 0.0) e.first->res.t_first_launch = t;
   for (auto& e : taken) e.first->outstanding += e.second;
+  if (taken.size() >= 2) s.st.shared_launches++;
+  int32_t in_flight = 0;
+  for (Req* q : s.active) in_flight += q->outstanding > 0;
+  s.st.max_in_flight = std::max(s.st.max_in_flight, in_flight);
   if (s.dry || sl.inject_fail) return true;
 
   for (auto& e : taken) JERK_HIP_CHECK(hipStreamWaitEvent(sl.stream, e.first->ready, 0));
@@ -478,7 +514,7 @@ void scheduler(jerk_server* sp) {
     try {
       // completions
       for (Slot& sl : s.slots) {
-        if (sl.busy && event_done(s, sl.done)) {
+        if (sl.busy && slot_done(s, sl)) {
           for (auto& e : sl.reqs) {
             e.first->outstanding -= e.second;
             if (sl.inject_fail && !e.first->failed) {
@@ -517,10 +553,20 @@ void scheduler(jerk_server* sp) {
       for (Slot& sl : s.slots)
         if (!sl.busy && dispatch(s, sl)) progressed = true;
     } catch (const Error& e) {
-      // device error: fail everything active; the server keeps accepting work
+      // Device error: fail everything active and release every busy slot, so the failed
+      // requests reach finalize (host-only for failed requests) and the stop exit stays
+      // reachable; the server keeps accepting work.
       for (Req* q : s.active) {
         q->failed = true;
         q->fail_status = e.status;
+      }
+      for (Slot& sl : s.slots) {
+        if (!sl.busy) continue;
+        if (!s.dry) (void)hipStreamSynchronize(sl.stream);  // its pinned table is free again
+        for (auto& r : sl.reqs) r.first->outstanding -= r.second;
+        sl.reqs.clear();
+        sl.busy = false;
+        sl.inject_fail = false;
       }
       progressed = true;
     }
@@ -551,6 +597,8 @@ void validate_request(const jerk_request& r) {
   require(!r.plane || (r.ld >= 2 * r.nbins && r.ld % 2 == 0), JERK_EINVAL, "plane ld must be even and >= 2 nbins");
   require(reinterpret_cast<uintptr_t>(r.spec) % 8 == 0 && reinterpret_cast<uintptr_t>(r.plane) % 8 == 0, JERK_EINVAL,
           "request buffers must be 8-byte aligned");
+  require(r.top_capacity >= 0 && (r.top != nullptr) == (r.top_capacity > 0), JERK_EINVAL,
+          "top must be set exactly when top_capacity > 0");
 }
 
 }  // namespace
@@ -653,12 +701,14 @@ void serve_stats(jerk_server& s, jerk_serve_stats* out) {
 }
 
 void serve_inject(jerk_server& s, int32_t op, int64_t n) {
-  require(op >= 1 && op <= 3, JERK_EINVAL, "op must be 1 (launch), 2 (bank build) or 3 (hold admission)");
+  require(op >= 1 && op <= 4, JERK_EINVAL,
+          "op must be 1 (launch), 2 (bank build), 3 (hold admission) or 4 (completion query errors)");
   require(n >= 0, JERK_EINVAL, "n must be >= 0");
   std::lock_guard<std::mutex> lock(s.mu);
   if (op == 1) s.fail_launch_at = n ? s.launch_count + n : 0;
   else if (op == 2) s.fail_build_at = n ? s.build_count + n : 0;
-  else s.paused = n != 0;
+  else if (op == 3) s.paused = n != 0;
+  else s.fail_queries = n;
   s.cv_sched.notify_all();
 }
 

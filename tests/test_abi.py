@@ -308,3 +308,43 @@ def test_batch_search_candidates_validates_on_the_host():
     # the second item needs more than the first: a workspace sized for the first is refused up front
     small = lib.jerk_search_candidates_workspace_bytes(plan.handle, 4096, 0, T, 2.7, 0)
     assert f(plan.handle, ws, items, 2, 0, T, 2.0, 2.7, 0, ws, small, None) == _lib.JERK_ENOMEM
+
+
+STRUCTS = {
+    "PlanDesc": "jerk_plan_desc", "PlanInfo": "jerk_plan_info_t", "GroupInfo": "jerk_group_info_t",
+    "BatchItem": "jerk_batch_item", "BatchCandItem": "jerk_batch_cand_item", "Peak": "jerk_peak",
+    "ServeDesc": "jerk_serve_desc", "Request": "jerk_request", "Top": "jerk_top", "Result": "jerk_result",
+    "ServeStats": "jerk_serve_stats",
+}
+
+
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets of its C struct."""
+    import shutil
+    import subprocess
+
+    from paper_1911_01353_amd import _lib
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(shutil.which("hipcc") or "/opt/rocm/bin/hipcc")))
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "jerk.h"', "int main(void) {"]
+    for py, c in STRUCTS.items():
+        lines.append(f'  printf("{py} size %zu\\n", sizeof({c}));')
+        for f, _ in getattr(_lib, py)._fields_:
+            lines.append(f'  printf("{py} {f} %zu\\n", offsetof({c}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I", inc, "-I", os.path.join(rocm, "include"),
+                    str(src), "-o", str(exe)], check=True, capture_output=True)
+    got = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    want = []
+    for py in STRUCTS:
+        cls = getattr(_lib, py)
+        want.append(f"{py} size {C.sizeof(cls)}")
+        want += [f"{py} {f} {getattr(cls, f).offset}" for f, _ in cls._fields_]
+    assert got[:-1] == want

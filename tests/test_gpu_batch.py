@@ -107,6 +107,36 @@ def test_graph_replays_match_eager(plan_bank, flat):
             assert np.array_equal(pa[0], pb[0]) and np.array_equal(pa[1], pb[1])
 
 
+@pytest.mark.parametrize("flat", [False, True])
+def test_reused_key_buffers_hold_no_stale_keys(plan_bank, flat):
+    """One key buffer per item, reused over graph replays with other spectra and never cleared by the
+    caller: the rows' tail keys (past a narrow group's segment count) are rewritten, so the peaks
+    equal each plane's row argmax. The buffers start filled with the largest possible key."""
+    import torch
+    plan, bank = plan_bank
+    T = plan.info()["n_templates"]
+    dev = device()
+    n = 30000
+    ws = torch.empty(plan.batch_workspace_bytes(2), dtype=torch.uint8, device=dev)
+    kpr = plan.keys_per_row(n)
+    keys = [torch.full((T, kpr + 5), -1, dtype=torch.int64, device=dev) for _ in range(2)]
+    for rep in range(3):
+        specs_np = _spectra([n, n], 300 + rep)
+        specs = [torch.from_numpy(x).to(dev) for x in specs_np]
+        planes = [torch.empty((T, 2 * n), dtype=torch.float32, device=dev) for _ in specs]
+        plan.batch_search(bank, list(zip(specs, planes, keys)), ws, 0, T, graph=True, flat=flat)
+        torch.cuda.synchronize()
+        for pl, k in zip(planes, keys):
+            red = torch.empty((T, 2), dtype=torch.int32, device=dev)
+            J.peaks_reduce(k, kpr, red)
+            torch.cuda.synchronize()
+            r = red.cpu().numpy()
+            hp, hi = _row_peaks(pl.cpu().numpy())
+            assert np.array_equal(r[:, 0].view(np.float32), hp) and np.array_equal(r[:, 1].astype(np.int64), hi)
+            tail = k[:, kpr:].cpu().numpy()
+            assert not tail.any(), "keys past jerk_batch_keys_per_row are not cleared"
+
+
 def test_batch_rejects_mixed_paths():
     device()
     plan = J.Plan(4096, 20.0, 60.0, 2.0, 20.0, path="auto")

@@ -42,13 +42,18 @@ def server():
     srv.close()
 
 
-def _submit(srv, specs, idx):
+def _submit(srv, specs, idx, top_k=0):
     out = []
     for i in idx:
         n, zm, wm, path, _ = REQS[i]
         T = Grid(zm, wm, 2.0, 20.0).n_templates
-        out.append(srv.submit(specs[i], zm, wm, path=path, n_templates=T))
+        out.append(srv.submit(specs[i], zm, wm, path=path, n_templates=T, top_k=top_k))
     return out
+
+
+def _top_from_peaks(power, p, k):
+    order = sorted(range(power.shape[0]), key=lambda t: (-float(power[t]), t))[:k]
+    return [(t, int(p[t]), float(power[t])) for t in order]
 
 
 def test_results_alone_equal_results_in_mix(server):
@@ -60,11 +65,29 @@ def test_results_alone_equal_results_in_mix(server):
         r = server.wait(t, 120.0)
         assert r is not None and r["status"] == J.JERK_OK
         alone.append(r)
-    # all at once, twice over, in an interleaved order
+    # all at once, twice over, in an interleaved order: admission is held until every request
+    # is queued, so the first three are admitted together and the rest as slots free up
     order = [0, 1, 2, 3, 2, 0, 3, 1]
-    tickets = _submit(server, specs, order)
+    st0 = server.stats()
+    server.inject_failure(3, 1)
+    tickets = _submit(server, specs, order, top_k=8)
+    server.inject_failure(3, 0)
     mixed = [server.wait(t, 120.0) for t in tickets]
+    st1 = server.stats()
+    # the requests' work overlapped on the device: launches carried units of several requests,
+    # and pairs of requests were in flight together (each started before the other finished)
+    assert st1["shared_launches"] > st0["shared_launches"], (st0, st1)
+    assert st1["max_in_flight"] >= 2
+    overlap = sum(1 for a in mixed for b in mixed if a is not b and a["t_first_launch"] < b["t_done"]
+                  and b["t_first_launch"] < a["t_done"])
+    print(f"[serve mix] shared launches {st1['shared_launches'] - st0['shared_launches']} of "
+          f"{st1['launches'] - st0['launches']}, overlapping pairs {overlap // 2}", flush=True)
+    assert overlap > 0
     for i, r in zip(order, mixed):
+        want = _top_from_peaks(r["peaks_power"], r["peaks_p"], 8)
+        assert r["top_count"] == 8
+        assert [(int(e["t"]), int(e["p"]), float(e["power"])) for e in r["top"]] == want
+        assert (int(r["top"][0]["t"]), int(r["top"][0]["p"])) == (r["best_t"], r["best_p"])
         assert r["status"] == J.JERK_OK
         a = alone[i]
         assert np.array_equal(r["peaks_power"].view(np.uint32), a["peaks_power"].view(np.uint32))

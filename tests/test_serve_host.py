@@ -97,3 +97,45 @@ def test_bad_descriptors():
         J.Server(FAKE_ARENA + 3, 1 << 30, dry_run=True)
     with pytest.raises(J.JerkError):
         J.Server(FAKE_ARENA, 1024, dry_run=True)
+
+
+def test_requests_in_flight_together_share_launches():
+    s = _server(max_active=3, queue_capacity=8)
+    s.inject_failure(3, 1)      # hold admission until all three are queued
+    tickets = [s.submit(FAKE_SPEC, 20, 60, nbins=1 << 18) for _ in range(3)]
+    s.inject_failure(3, 0)
+    assert all(s.wait(t, 10.0)["status"] == J.JERK_OK for t in tickets)
+    st = s.stats()
+    assert st["shared_launches"] >= 1 and st["max_in_flight"] >= 2
+    s.close()
+
+
+def test_top_k_has_k_distinct_templates_in_order():
+    s = _server(max_active=1)
+    t = s.submit(FAKE_SPEC, 20, 60, nbins=1 << 16, top_k=5)
+    r = s.wait(t, 10.0)
+    assert r["status"] == J.JERK_OK and r["top_count"] == 5
+    # dry run: every row peak has power 0, so ties go to the lowest templates
+    assert list(r["top"]["t"]) == [0, 1, 2, 3, 4]
+    with pytest.raises(J.JerkError):
+        s.submit(FAKE_SPEC, 20, 60, nbins=1 << 16, top_k=-1)
+    s.close()
+
+
+def test_device_error_in_completion_query_fails_in_flight_requests_and_server_recovers():
+    """A completion query that reports a device error (as a sticky fault would) ends every request
+    with work in flight with EHIP, releases the launch slots and leaves the server running."""
+    s = _server(max_active=2, queue_capacity=8)
+    s.inject_failure(3, 1)
+    s.inject_failure(4, 1 << 30)    # every completion query fails until disarmed
+    bad = [s.submit(FAKE_SPEC, 20, 60, nbins=1 << 16) for _ in range(3)]
+    s.inject_failure(3, 0)
+    res = [s.wait(t, 10.0) for t in bad]
+    assert all(r is not None and r["status"] == J.JERK_EHIP for r in res)
+    s.inject_failure(4, 0)
+    good = s.submit(FAKE_SPEC, 20, 60, nbins=1 << 16)
+    r = s.wait(good, 10.0)
+    assert r is not None and r["status"] == J.JERK_OK
+    st = s.stats()
+    assert st["failed"] == 3 and st["completed"] == 1 and st["active"] == 0
+    s.close()
