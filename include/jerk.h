@@ -237,6 +237,21 @@ int32_t jerk_search_peaks(const jerk_plan* plan, const void* d_bank, const void*
                           int32_t t_begin, int32_t t_end, jerk_peak* d_out, void* d_ws, size_t ws_bytes,
                           hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): jerk_search_peaks with its key workspace in a
+ * fixed library-owned device array of JERK_NOALLOC_MAX_ROWS keys (8 bytes each, 256 KiB on
+ * every GPU the library runs on, held until the process ends) instead of a caller buffer.
+ * Allocates nothing: no hipMalloc, hipFree or allocating library call; the first call on a
+ * device looks up that device's copy of the array. The keys are cleared by a kernel at the
+ * start of every call. Results equal jerk_search_peaks's bit for bit. EINVAL when
+ * t_end - t_begin exceeds JERK_NOALLOC_MAX_ROWS (split the range into several calls), and
+ * as jerk_search_peaks otherwise. Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads) race, and the caller must serialise them.
+ * Asynchronous on stream. */
+#define JERK_NOALLOC_MAX_ROWS 32768
+int32_t jerk_search_peaks_noalloc(const jerk_plan* plan, const void* d_bank, const void* d_spec, int64_t nbins,
+                                  int32_t t_begin, int32_t t_end, jerk_peak* d_out, hipStream_t stream);
+
 /* Reduces peak keys [rows][keys_ld] (first keys_per_row of each row) to one jerk_peak per row.
  * Rows whose keys were all left 0 report power 0 and p = 0xFFFFFFFF. Asynchronous on stream. */
 int32_t jerk_peaks_reduce(const uint64_t* d_keys, int32_t rows, int64_t keys_per_row, int64_t keys_ld,

@@ -14,12 +14,13 @@ import numpy as np
 
 from . import _lib
 from ._lib import (JERK_EAGAIN, JERK_ECANCELED, JERK_EHIP, JERK_EINVAL, JERK_ENOMEM, JERK_EPENDING, JERK_OK,
-                   PATH_AUTO, PATH_FFT_FP32, PATH_GEMM_FP16, PATH_GEMM_SPLIT_BF16, PATH_NAMES, JerkError)
+                   NOALLOC_MAX_ROWS, PATH_AUTO, PATH_FFT_FP32, PATH_GEMM_FP16, PATH_GEMM_SPLIT_BF16, PATH_NAMES,
+                   JerkError)
 
 __all__ = [
     "Plan", "Server", "peaks_reduce", "stream_check", "stats_workspace_bytes", "plane_stats", "find_candidates",
     "candidates_numpy", "CANDIDATE_DTYPE", "peaks_numpy", "PEAK_DTYPE", "spectrum_workspace_bytes", "prepare_spectrum", "JERK_EHIP", "JERK_ECANCELED", "JerkError", "load", "version", "PATH_FFT_FP32", "PATH_GEMM_SPLIT_BF16", "PATH_GEMM_FP16",
-    "PATH_AUTO", "PATH_NAMES", "JERK_OK", "JERK_EINVAL", "JERK_ENOMEM", "JERK_EAGAIN", "JERK_EPENDING",
+    "PATH_AUTO", "PATH_NAMES", "NOALLOC_MAX_ROWS", "JERK_OK", "JERK_EINVAL", "JERK_ENOMEM", "JERK_EAGAIN", "JERK_EPENDING",
 ]
 
 
@@ -234,6 +235,21 @@ class Plan:
         _lib.check(_lib.load().jerk_search_peaks(self.handle, _dev_ptr(bank), _dev_ptr(spec), spec.shape[0], t_begin,
                                                  t_end, _dev_ptr(out), _dev_ptr(ws), ws.numel() * ws.element_size(),
                                                  _stream_ptr(stream)))
+        return out
+
+    def search_peaks_noalloc(self, bank, spec, out, t_begin: int = 0, t_end: int | None = None, stream=None):
+        """Enqueue ``jerk_search_peaks_noalloc``: ``search_peaks`` with the library's fixed device
+        workspace (at most ``NOALLOC_MAX_ROWS`` rows per call); allocates nothing, so ``out`` (a
+        contiguous (rows, 2) int32 device tensor) is required. Calls on one GPU must not overlap."""
+        import torch
+        if spec.dtype != torch.complex64 or spec.dim() != 1 or not spec.is_contiguous():
+            raise ValueError("spec must be a contiguous 1-D complex64 tensor")
+        if t_end is None:
+            t_end = self.info()["n_templates"]
+        if out.shape[0] < t_end - t_begin or out.shape[1] != 2 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous (rows, 2) tensor")
+        _lib.check(_lib.load().jerk_search_peaks_noalloc(self.handle, _dev_ptr(bank), _dev_ptr(spec), spec.shape[0],
+                                                         t_begin, t_end, _dev_ptr(out), _stream_ptr(stream)))
         return out
 
     def batch_search_candidates(self, bank, items, k_sigma: float, pre_level: float | None = None,

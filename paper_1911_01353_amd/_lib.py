@@ -22,6 +22,7 @@ JERK_EHIP = -5
 JERK_EUNSUPPORTED = -6
 JERK_EINTERNAL = -7
 JERK_ECANCELED = -8
+NOALLOC_MAX_ROWS = 32768  # JERK_NOALLOC_MAX_ROWS
 
 PATH_FFT_FP32 = 0
 PATH_GEMM_SPLIT_BF16 = 1
@@ -161,6 +162,8 @@ SIGNATURES = {
                                                   C.c_int32, C.c_double, C.c_double, C.c_int64, C.c_void_p, C.c_size_t,
                                                   C.c_void_p]),
     "jerk_search_peaks_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int32, C.c_int32]),
+    "jerk_search_peaks_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                              C.c_void_p, C.c_void_p]),
     "jerk_search_peaks": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
                                       C.c_void_p, C.c_size_t, C.c_void_p]),
     "jerk_search_candidates_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_double,

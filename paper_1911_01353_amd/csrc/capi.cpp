@@ -4,6 +4,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -497,6 +498,50 @@ int32_t jerk_search_peaks(const jerk_plan* plan, const void* d_bank, const void*
     const int32_t rows = t_end - t_begin;
     require(ws_bytes >= (size_t)rows * sizeof(uint64_t), JERK_ENOMEM, "peak workspace too small");
     uint64_t* keys = static_cast<uint64_t*>(d_ws);
+    jerk::fill_u64(keys, rows, 0ull, stream);
+    jerk::search_enqueue(p, d_bank, d_spec, nbins, nullptr, 2 * nbins, t_begin, t_end, 0, (int32_t)p.groups.size(),
+                         stream, keys);
+    jerk::peaks_reduce(keys, rows, 1, 1, d_out, stream);
+  });
+}
+
+namespace {
+// Key workspace of jerk_search_peaks_noalloc: one copy per GPU, found by symbol lookup.
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) uint64_t scratch[JERK_NOALLOC_MAX_ROWS];
+std::mutex g_scratch_mu;
+uint64_t* g_scratch[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch` (looked up once per device).
+uint64_t* scratch_on_current_device() {
+  int dev = 0;
+  JERK_HIP_CHECK(hipGetDevice(&dev));
+  require(dev >= 0 && dev < kMaxDevices, JERK_EUNSUPPORTED, "device index beyond the no-allocation table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev] == nullptr) {
+    void* ptr = nullptr;
+    JERK_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    require(ptr != nullptr, JERK_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch[dev] = static_cast<uint64_t*>(ptr);
+  }
+  return g_scratch[dev];
+}
+}  // namespace
+
+int32_t jerk_search_peaks_noalloc(const jerk_plan* plan, const void* d_bank, const void* d_spec, int64_t nbins,
+                                  int32_t t_begin, int32_t t_end, jerk_peak* d_out, hipStream_t stream) {
+  return guarded([&] {
+    require(plan != nullptr, JERK_EINVAL, "plan must not be NULL");
+    const jerk::Plan& p = plan->p;
+    require(0 <= t_begin && t_begin <= t_end && t_end <= p.T, JERK_EINVAL, "template range outside [0, n_templates]");
+    if (t_begin == t_end) return;
+    require(d_bank && d_spec && d_out, JERK_EINVAL, "bank, spectrum and output must not be NULL");
+    require(nbins >= 1 && nbins < (int64_t(1) << 31), JERK_EINVAL, "nbins must be in [1, 2^31)");
+    require(reinterpret_cast<uintptr_t>(d_spec) % 8 == 0, JERK_EINVAL, "spectrum must be 8-byte aligned");
+    const int32_t rows = t_end - t_begin;
+    require(rows <= JERK_NOALLOC_MAX_ROWS, JERK_EINVAL,
+            "t_end - t_begin exceeds JERK_NOALLOC_MAX_ROWS (32768): split the template range");
+    uint64_t* keys = scratch_on_current_device();  // never the array's name: a host-side stand-in
     jerk::fill_u64(keys, rows, 0ull, stream);
     jerk::search_enqueue(p, d_bank, d_spec, nbins, nullptr, 2 * nbins, t_begin, t_end, 0, (int32_t)p.groups.size(),
                          stream, keys);
