@@ -198,9 +198,13 @@ typedef struct jerk_batch_item {
                         clearing between calls                                          */
 } jerk_batch_item;
 
-#define JERK_BATCH_GRAPH 1u /* capture the launch in a hipGraph on first use and replay it */
-#define JERK_BATCH_FLAT 2u  /* one flat launch (a workgroup per tile, the hardware dispatcher balancing
-                               the load) instead of the persistent kernel; same results bit for bit */
+#define JERK_BATCH_GRAPH 1u      /* capture the launch in a hipGraph on first use and replay it     */
+#define JERK_BATCH_FLAT 2u       /* one flat launch: a workgroup per tile, the hardware dispatcher
+                                    balancing the load (the default; the flag only states it)      */
+#define JERK_BATCH_PERSISTENT 4u /* one persistent launch instead: a full-device grid whose
+                                    workgroups take tiles from a device counter until none is left;
+                                    same results bit for bit, slower (its tile loop costs registers
+                                    and so waves per SIMD)                                         */
 
 /* Workspace bytes jerk_batch_search needs for up to `count` items. */
 size_t jerk_batch_workspace_bytes(const jerk_plan* plan, int32_t count);
@@ -208,9 +212,11 @@ size_t jerk_batch_workspace_bytes(const jerk_plan* plan, int32_t count);
  * is (float bits of the power << 32) | (0xFFFFFFFF - p): the largest key of a row is its
  * peak power, ties going to the lowest r index p (jerk_peaks_reduce turns keys into peaks). */
 int64_t jerk_batch_keys_per_row(const jerk_plan* plan, int64_t nbins);
-/* Searches rows [t_begin, t_end) of every item in ONE persistent kernel launch: workgroups
- * take (spectrum, width group, template block, segment) tiles from a device counter until
- * all are done. All width groups must be on the FFT path with one segment length.
+/* Searches rows [t_begin, t_end) of every item in ONE kernel launch over a job table of
+ * (spectrum, width group, template block, segment) tiles: by default a flat launch (one
+ * workgroup per tile), with JERK_BATCH_PERSISTENT a persistent kernel whose workgroups take
+ * tiles from a device counter until all are done. All width groups must be on the FFT path
+ * with one segment length.
  * Results equal jerk_search's bit for bit. With JERK_BATCH_GRAPH the launch is captured in
  * a hipGraph the first time (per plan, workspace and device) and replayed afterwards; the
  * job table is rewritten before every replay. Overlapping calls on one plan serialise on

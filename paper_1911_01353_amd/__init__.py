@@ -185,12 +185,13 @@ class Plan:
         return int(_lib.load().jerk_batch_keys_per_row(self.handle, nbins))
 
     def batch_search(self, bank, items, ws, t_begin: int = 0, t_end: int | None = None, graph: bool = False,
-                     flat: bool = False, stream=None) -> None:
+                     flat: bool = True, stream=None) -> None:
         """Enqueue ``jerk_batch_search`` over ``items``: (spec, plane or None, peak keys or None).
 
         ``plane``: float32 (rows, >= 2n); ``keys``: uint64-sized (rows, >= keys_per_row(n))
-        tensor (torch.int64 storage, zero-filled by the caller). ``flat``: one flat launch
-        (JERK_BATCH_FLAT) instead of the persistent kernel.
+        tensor (torch.int64 storage; every key of a row is written, so no clearing is needed).
+        ``flat``: one flat launch (the default); ``flat=False``: the persistent kernel
+        (JERK_BATCH_PERSISTENT).
         """
         if t_end is None:
             t_end = self.info()["n_templates"]
@@ -205,7 +206,7 @@ class Plan:
             arr[i].keys_ld = keys.stride(0) if keys is not None else 0
         _lib.check(_lib.load().jerk_batch_search(self.handle, _dev_ptr(bank), arr, len(items), t_begin, t_end,
                                                  _dev_ptr(ws), ws.numel() * ws.element_size(),
-                                                 (_lib.BATCH_GRAPH if graph else 0) | (_lib.BATCH_FLAT if flat else 0),
+                                                 (_lib.BATCH_GRAPH if graph else 0) | (_lib.BATCH_FLAT if flat else _lib.BATCH_PERSISTENT),
                                                  _stream_ptr(stream)))
 
     def harmonic_shape(self, n_r: int, n_harm: int) -> tuple:

@@ -11,7 +11,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libjerk.so")
+# JERK_LIBRARY selects another build of the same library (the host-sanitized libjerk_asan.so)
+LIB_PATH = os.environ.get("JERK_LIBRARY") or os.path.join(HERE, "libjerk.so")
 
 JERK_OK = 0
 JERK_EINVAL = -1
@@ -80,6 +81,7 @@ class Peak(C.Structure):
 
 BATCH_GRAPH = 1
 BATCH_FLAT = 2
+BATCH_PERSISTENT = 4
 SERVE_DRYRUN = 1
 
 

@@ -83,8 +83,10 @@ void batch_search(Plan& p, const void* d_bank, const jerk_batch_item* items, int
   require(d_bank != nullptr, JERK_EINVAL, "bank must not be NULL");
   require(count >= 0 && (count == 0 || items != nullptr), JERK_EINVAL, "items must not be NULL");
   require(0 <= t_begin && t_begin <= t_end && t_end <= p.T, JERK_EINVAL, "template range outside [0, n_templates]");
-  require((flags & ~(JERK_BATCH_GRAPH | JERK_BATCH_FLAT)) == 0, JERK_EINVAL, "unknown flags");
-  const bool flat = (flags & JERK_BATCH_FLAT) != 0;
+  require((flags & ~(JERK_BATCH_GRAPH | JERK_BATCH_FLAT | JERK_BATCH_PERSISTENT)) == 0, JERK_EINVAL, "unknown flags");
+  require((flags & JERK_BATCH_FLAT) == 0 || (flags & JERK_BATCH_PERSISTENT) == 0, JERK_EINVAL,
+          "JERK_BATCH_FLAT and JERK_BATCH_PERSISTENT exclude each other");
+  const bool flat = (flags & JERK_BATCH_PERSISTENT) == 0;
   const auto var = uniform_variant(p);
   const int32_t seg = var.first, ept = var.second;
   const size_t need = jobs_capacity_bytes(p, count);

@@ -83,6 +83,18 @@ void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64
     else if (n_pending > 1) gemm_correlate_multi_launch(pending, n_pending, stream);
     n_pending = 0;
   };
+  // FFT-path groups of one kernel variant (segment length, elements per thread) go out
+  // together too, up to kFftArgJobs per launch: one launch and one tail instead of one per group
+  FftJob fpend[kFftArgJobs];
+  int n_fpend = 0, f_seg = 0, f_ept = 0;
+  int64_t f_tiles = 0;  // tiles of the pending jobs (one launch stays below 2^31 workgroups)
+  const float2* f_tw = nullptr;
+  auto fflush = [&]() {
+    if (n_fpend == 1) fft_correlate_launch(fpend[0], f_seg, f_ept, f_tw, stream);
+    else if (n_fpend > 1) fft_args_launch(fpend, n_fpend, f_seg, f_ept, row_max != nullptr, f_tw, stream);
+    n_fpend = 0;
+    f_tiles = 0;
+  };
   for (int32_t gi = g_begin; gi < g_end; ++gi) {
     const Group& g = p.groups[gi];
     int32_t lo, hi;
@@ -103,8 +115,15 @@ void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64
       j.tpb = g.tpb;
       j.row_max = row_max;
       j.rmax_ld = 0;
-      fft_correlate_launch(j, g.seg_len, g.ept, reinterpret_cast<const float2*>(bank + p.off_tw[tw_slot(g.seg_len)]),
-                           stream);
+      const int64_t U = g.seg_len - g.taps + 1;
+      const int64_t tiles = (nbins + U - 1) / U * ((hi - lo + g.tpb - 1) / g.tpb);
+      if (n_fpend > 0 && (f_seg != g.seg_len || f_ept != g.ept || f_tiles + tiles >= (1ll << 31))) fflush();
+      f_tiles += tiles;
+      f_seg = g.seg_len;
+      f_ept = g.ept;
+      f_tw = reinterpret_cast<const float2*>(bank + p.off_tw[tw_slot(g.seg_len)]);
+      fpend[n_fpend++] = j;
+      if (n_fpend == kFftArgJobs) fflush();
     } else {
       GemmArgs a{};
       a.spec = static_cast<const float2*>(d_spec);
@@ -130,6 +149,7 @@ void search_enqueue(const Plan& p, const void* d_bank, const void* d_spec, int64
     }
   }
   flush();
+  fflush();
 }
 
 // Rows [m_begin, m_end) of group g's member list, output row = member - m_begin.

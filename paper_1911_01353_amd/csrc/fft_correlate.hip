@@ -602,6 +602,26 @@ __global__ void __launch_bounds__(S / E) fft_multi_kernel(const FftJob* __restri
   fft_tile<S, E, R1, R2, R3, R4, KEYS, 0, true>(j, local % j.n_seg, m0, min(m0 + j.tpb, j.m_end), lds, red, tw);
 }
 
+// Several jobs of one variant in one flat launch, the job table travelling in the kernel
+// arguments: workgroup i takes tile i of the job whose tile range holds it.
+struct FftArgJobs {
+  FftJob job[kFftArgJobs];
+  int32_t n;
+};
+
+template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS>
+__global__ void __launch_bounds__(S / E) fft_args_kernel(FftArgJobs m, const float2* __restrict__ tw) {
+  __shared__ float2 lds[S + S / 16];
+  __shared__ uint64_t red[8];
+  const int64_t tile = blockIdx.x;
+  int k = 0;
+  while (k + 1 < m.n && tile >= m.job[k + 1].tile_begin) ++k;
+  const FftJob& j = m.job[k];
+  const int64_t local = tile - j.tile_begin;
+  const int m0 = j.m_begin + (int)(local / j.n_seg) * j.tpb;
+  fft_tile<S, E, R1, R2, R3, R4, KEYS, 0, true>(j, local % j.n_seg, m0, min(m0 + j.tpb, j.m_end), lds, red, tw);
+}
+
 // Candidate passes over one width-group job (cand_epilogue). Mode 1: one
 // workgroup per tile (template block, segment), as fft_correlate_kernel. Mode 2:
 // the flagged rows, one template per tile, the grid striding over (flagged row,
@@ -753,6 +773,36 @@ void fft_persistent_launch(const FftJob* d_jobs, BatchHeader* d_hdr, int32_t seg
     else                                                                                                          \
       hipLaunchKernelGGL((fft_persistent_kernel<S, E, A, B, C, D, false>), dim3(grid), dim3(S / E), 0, stream,    \
                          d_jobs, d_hdr, twiddles);                                                                \
+    JERK_HIP_CHECK(hipGetLastError());                                                                            \
+    return;                                                                                                       \
+  }
+  JERK_FFT_VARIANTS(X)
+#undef X
+  throw Error(JERK_EINTERNAL, "unsupported FFT kernel variant");
+}
+
+void fft_args_launch(FftJob* jobs, int n, int32_t seg_len, int32_t ept, bool keys, const float2* twiddles,
+                     hipStream_t stream) {
+  require(n >= 1 && n <= kFftArgJobs, JERK_EINTERNAL, "fft_args_launch takes 1..8 jobs");
+  FftArgJobs m{};
+  int64_t total = 0;
+  for (int k = 0; k < n; ++k) {
+    m.job[k] = jobs[k];
+    m.job[k].tile_begin = total;
+    total += fft_job_tiles(m.job[k], seg_len);
+    require((m.job[k].row_max != nullptr) == keys, JERK_EINTERNAL, "every job of one launch keys or none does");
+  }
+  m.n = n;
+  if (total == 0) return;
+  require(total < (int64_t(1) << 31), JERK_EINVAL, "search too large for one launch; split the template range");
+#define X(S, E, A, B, C, D)                                                                                       \
+  if (seg_len == S && ept == E) {                                                                                 \
+    if (keys)                                                                                                     \
+      hipLaunchKernelGGL((fft_args_kernel<S, E, A, B, C, D, true>), dim3((unsigned)total), dim3(S / E), 0, stream, \
+                         m, twiddles);                                                                            \
+    else                                                                                                          \
+      hipLaunchKernelGGL((fft_args_kernel<S, E, A, B, C, D, false>), dim3((unsigned)total), dim3(S / E), 0,       \
+                         stream, m, twiddles);                                                                    \
     JERK_HIP_CHECK(hipGetLastError());                                                                            \
     return;                                                                                                       \
   }

@@ -502,14 +502,16 @@ struct GemmGrid {
 };
 
 // Workgroups of one job: RB row blocks of 8 templates each by runs of consecutive windows of
-// 32 CT outputs, about 4096 workgroups (4 waves' worth per CU slot) or fewer.
+// 32 CT outputs, about 16384 workgroups (16 one-wave workgroups per SIMD over the launch) or
+// fewer: narrow groups have few row blocks, and 4096 left them at 2-3 waves per SIMD for the
+// whole launch (the 48-tap group of the 2^22-bin search: 6.1e11 -> 7.1e11 points/s).
 GemmGrid gemm_grid(const GemmArgs& a, int RB, int CT) {
   const int n_members = a.m_end - a.m_begin;
   const int cols = 32 * CT;
   const int64_t n_win = (a.nbins + cols - 1) / cols;
   const int64_t n_tblk = (n_members + 8 * RB - 1) / (8 * RB);
   int64_t wpw = 1;
-  while (n_tblk * ((n_win + wpw - 1) / wpw) > 4096 && wpw < 256) wpw *= 2;
+  while (n_tblk * ((n_win + wpw - 1) / wpw) > 16384 && wpw < 256) wpw *= 2;
   const int64_t ncc = (n_win + wpw - 1) / wpw;
   return {wpw, ncc, n_tblk * ncc};
 }

@@ -191,6 +191,11 @@ void fft_correlate_launch(FftJob j, int32_t seg_len, int32_t ept, const float2* 
 // One flat launch over a job table: grid = total tiles, workgroup i takes tile i.
 void fft_multi_launch(const FftJob* d_jobs, const BatchHeader* d_hdr, int64_t total, int32_t seg_len, int32_t ept,
                       bool keys, const float2* twiddles, hipStream_t stream);
+// Up to kFftArgJobs jobs of one kernel variant in one flat launch, the job table in the kernel
+// arguments (no device buffer): every job's keys flag must match `keys`.
+constexpr int kFftArgJobs = 8;
+void fft_args_launch(FftJob* jobs, int n, int32_t seg_len, int32_t ept, bool keys, const float2* twiddles,
+                     hipStream_t stream);
 void fft_persistent_launch(const FftJob* d_jobs, BatchHeader* d_hdr, int32_t seg_len, int32_t ept, bool keys,
                            const float2* twiddles, int32_t grid, hipStream_t stream);
 // Workgroups of the persistent kernel that fit on the current device at once.

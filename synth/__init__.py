@@ -11,6 +11,7 @@ from .spectra import (
     SearchConfig,
     CONFIGS,
     time_series,
+    time_series_device,
     spectrum_from_series,
     make_spectrum,
     draw_tones,
@@ -23,6 +24,7 @@ __all__ = [
     "SearchConfig",
     "CONFIGS",
     "time_series",
+    "time_series_device",
     "spectrum_from_series",
     "make_spectrum",
     "draw_tones",

@@ -85,6 +85,24 @@ def spectrum_from_series(x: np.ndarray) -> np.ndarray:
     return spec.astype(np.complex64)
 
 
+def time_series_device(n_samples: int, seed: int, tones=(), device="cuda"):
+    """``time_series``'s recipe generated on a device with torch, for batches too large to
+    build on the host: N(0, 1) float32 noise from torch's generator seeded with ``seed`` (a
+    different stream from numpy's), each tone added in float64, the sum rounded once to float32."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    x = torch.randn(n_samples, device=device, generator=g, dtype=torch.float32)
+    if tones:
+        u = torch.arange(n_samples, device=device, dtype=torch.float64) / n_samples
+        acc = x.double()
+        for t in tones:
+            ph = 2.0 * math.pi * (t.r0 * u + t.z0 * u * u / 2.0 + t.w0 * u * u * u / 6.0) + t.phi0
+            acc += t.amp * torch.cos(ph)
+        x = acc.float()
+    return x.contiguous()
+
+
 def make_spectrum(cfg: SearchConfig) -> np.ndarray:
     return spectrum_from_series(time_series(cfg.n_samples, cfg.seed, cfg.tones))
 
