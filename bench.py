@@ -31,8 +31,6 @@ HBM_PEAK_GBS = 8000.0
 MFMA_BF16_TFLOPS = 2500.0
 MFMA_FP16_TFLOPS = 2500.0
 FP32_VECTOR_PUBLISHED_TFLOPS = 157.3
-# FP32 vector FMA without packed (dual) FP32 issue: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz.
-FP32_VECTOR_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 def parse():
@@ -48,8 +46,10 @@ def parse():
                     help="templates (full rows) in the oracle's timed sample; 0 skips cpu_baseline")
     ap.add_argument("--errors", type=int, default=1, help="measure plane errors on the 2^15-bin search")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the plan before timing (untimed)")
-    ap.add_argument("--serve-requests", type=int, default=48,
-                    help="requests per serving pass (cold then warm template cache); 0 skips serving")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests per warm serving pass (one per offered load); 0 skips serving")
+    ap.add_argument("--serve-cold-requests", type=int, default=48,
+                    help="requests of the cold closed-loop pass that measures the service rate")
     ap.add_argument("--serve-load", default="0.5,0.8",
                     help="offered loads (arrival rate / service rate), comma-separated: one warm pass each")
     ap.add_argument("--batch-items", type=int, default=256,
@@ -64,7 +64,7 @@ def parse():
                     help="time the whole search with fused candidate selection (no plane) this many times "
                          "(0 = skip)")
     ap.add_argument("--harm-templates", type=int, default=1,
-                    help="time harmonic sums (H = 2, 4, 8) over a 147-template plane of the 2^22-bin spectrum")
+                    help="time harmonic sums (H = 2, 4, 8) over a 1159-template plane of the 2^22-bin spectrum")
     ap.add_argument("--prep", type=int, default=1,
                     help="time the device spectrum preparation of a 2^23-sample series")
     ap.add_argument("--small-reps", type=int, default=200,
@@ -212,6 +212,23 @@ def kernel_table(ks):
                 "tflops": v["flops"] / v["time"] / 1e12, "hbm_GBps": v["bytes"] / v["time"] / 1e9,
                 **({"mfma_frac": v["flops"] / v["time"] / 1e12 / MFMA_BF16_TFLOPS} if v["path"] else {})}
             for k, v in ks.items()}
+
+
+def peak_probe():
+    """Measured arithmetic ceilings (MFMA bf16, FP32 FMA) from the package's peakprobe program,
+    run as a child process; None when it has not been built."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1911_01353_amd", "peakprobe")
+    if not os.path.exists(exe):
+        return None
+    res = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    if res.returncode != 0:
+        print(f"[bench] peakprobe failed: {res.stderr.strip()}", file=sys.stderr, flush=True)
+        return None
+    out = json.loads(res.stdout)
+    out["what"] = ("v_mfma_f32_32x32x16_bf16 and v_fma_f32 loops with no memory traffic over every SIMD at "
+                   "8 waves per SIMD (paper_1911_01353_amd/peakprobe.hip), best of 3, HIP events")
+    return out
 
 
 def hbm_copy_leg(torch, gib=4.0, reps=10):
@@ -467,15 +484,17 @@ def harmonic_touched_bytes(plan, n_r, H):
 
 
 def harmonics_leg(J, torch, spec, n, reps=5):
-    """Harmonic sums of the full plane of a 147-template grid (zmax 20, wmax 60) of the 2^22-bin
-    spectrum (4.9 GB), for H = 2, 4, 8; algorithmic bytes 4 (H + 1) per output point."""
-    plan = J.Plan(n, 20.0, 60.0, 2.0, 20.0, path="fft")
+    """Harmonic sums of the full plane of a 61 x 19 = 1159-template grid (zmax 60, wmax 180) of the
+    2^22-bin spectrum (38.9 GB), for H = 2, 4, 8 (279, 75 and 21 fundamental rows of 2^23 / H
+    points); algorithmic bytes 4 (H + 1) per output point. Harmonic h reads its row at stride h,
+    so the bytes of the 128-byte lines touched are reported beside them."""
+    plan = J.Plan(n, 60.0, 180.0, 2.0, 20.0, path="fft")
     bank = plan.new_bank()
     plan.build_templates(bank)
     T = plan.info()["n_templates"]
     plane = torch.empty((T, 2 * n), dtype=torch.float32, device="cuda")
     plan.search(bank, spec, plane, 0, T)
-    res = {"workload": f"full plane of {T} templates (zmax 20, wmax 60) x {2 * n} points"}
+    res = {"workload": f"full plane of {T} templates (zmax 60, wmax 180) x {2 * n} points"}
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     for H in (2, 4, 8):
         out = plan.harmonic_sum(plane, H)
@@ -645,15 +664,15 @@ def plane_errors(J, torch):
     return res
 
 
-def serving_leg(J, torch, n_req, load):
+def serving_leg(J, torch, n_req, load, n_cold=48, top_k=10):
     """Poisson stream of search requests (lengths 2^18..2^23 bins, zmax 50..300, wmax 3 zmax,
-    FP32 / split-BF16 half and half) through the request server: all at once with a cold
-    template cache (the service rate), then the same stream at each offered load with every
-    grid's bank resident. Latency is host time from submit to completion; with n_req requests
-    the p99.9 is the largest latency once n_req < 1000."""
+    FP32 / split-BF16 half and half) through the request server: n_cold of them all at once with a
+    cold template cache (the service rate), then n_req at each offered load with every grid's bank
+    resident. Latency is host time from submit to completion, reported over all requests and per
+    path; every request also returns its global top-k (k row peaks)."""
     import numpy as np
     import synth
-    reqs = synth.serving_requests(n_req, 1.0)
+    reqs = synth.serving_requests(max(n_req, n_cold), 1.0)
     # one resident spectrum per length class (seeded), shared by the requests of that length
     specs = {}
     for r in reqs:
@@ -661,12 +680,16 @@ def serving_leg(J, torch, n_req, load):
             x = synth.time_series(r["n_samples"], r["seed"], r["tones"])
             specs[r["n_samples"]] = torch.from_numpy(synth.spectrum_from_series(x)).cuda()
     arena = torch.empty(96 << 30, dtype=torch.uint8, device="cuda")
-    srv = J.Server(arena, max_active=4, queue_capacity=4 * n_req, tiles_per_launch=1 << 16)
+    srv = J.Server(arena, max_active=4, queue_capacity=4 * len(reqs), tiles_per_launch=1 << 16)
 
-    def run_pass(rate):
+    def stats(lat, pts):
+        return {"requests": len(lat), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                "max_s": float(lat.max()), "request_points_per_s": float(pts.sum() / lat.sum())}
+
+    def run_pass(rs, rate):
         t0 = time.perf_counter()
         tickets = []
-        for r in reqs:
+        for r in rs:
             due = t0 + r["arrival_s"] / rate
             while True:
                 now = time.perf_counter()
@@ -674,47 +697,64 @@ def serving_leg(J, torch, n_req, load):
                     break
                 time.sleep(min(0.002, due - now))
             tickets.append(srv.submit(specs[r["n_samples"]], r["zmax"], r["wmax"], r["dz"], r["dw"],
-                                      path="split_bf16" if r["split_bf16"] else "fft"))
+                                      path="split_bf16" if r["split_bf16"] else "fft", top_k=top_k))
+            if len(tickets) % 50 == 0:
+                print(f"[bench] serving: {len(tickets)} of {len(rs)} submitted", file=sys.stderr, flush=True)
         res = [srv.wait(t, 600.0) for t in tickets]
         wall = time.perf_counter() - t0
         lat = np.array([x["t_done"] - x["t_submit"] for x in res])
-        pts = sum(x["points"] for x in res)
-        ok = all(x["status"] == 0 for x in res)
-        return {"requests": len(res), "ok": ok, "p50_s": float(np.percentile(lat, 50)),
-                "p99_s": float(np.percentile(lat, 99)), "p99.9_s": float(np.percentile(lat, 99.9)),
-                "max_s": float(lat.max()), "wall_s": wall, "points_per_s": pts / wall, "points": pts}
+        pts = np.array([x["points"] for x in res], dtype=np.float64)
+        ok = all(x["status"] == 0 for x in res) and all(x["top_count"] == top_k for x in res)
+        split = np.array([r["split_bf16"] for r in rs])
+        out = {"requests": len(res), "ok": ok, "p50_s": float(np.percentile(lat, 50)),
+               "p99_s": float(np.percentile(lat, 99)), "p99.9_s": float(np.percentile(lat, 99.9)),
+               "max_s": float(lat.max()), "wall_s": wall, "points_per_s": float(pts.sum() / wall),
+               "points": float(pts.sum())}
+        for name, sel in (("fft", ~split), ("split_bf16", split)):
+            if sel.any():
+                out[name] = stats(lat[sel], pts[sel])
+        return out
 
-    # service rate from the mean request size and a closed-loop pass (cold cache)
-    cold = run_pass(1e9)   # all at once: measures the service capacity with cold banks
+    st0 = srv.stats()
+    cold = run_pass(reqs[:n_cold], 1e9)   # all at once: the service capacity with cold banks
     mu = cold["requests"] / cold["wall_s"]
+    print(f"[bench] serving: cold pass {cold['wall_s']:.1f} s, service rate {mu:.2f} requests/s", file=sys.stderr,
+          flush=True)
     warm = {}
     for rho in load:
-        warm[f"{rho:g}"] = dict(run_pass(rho * mu), load=rho, arrival_rate_hz=rho * mu)
+        warm[f"{rho:g}"] = dict(run_pass(reqs[:n_req], rho * mu), load=rho, arrival_rate_hz=rho * mu)
+        w = warm[f"{rho:g}"]
+        print(f"[bench] serving: load {rho:g}: p50 {w['p50_s']:.2f} s, p99 {w['p99_s']:.2f} s", file=sys.stderr,
+              flush=True)
     st = srv.stats()
     srv.close()
     del arena
     return {"loads": list(load), "service_rate_hz": mu, "cold_closed_loop": cold, "warm_poisson": warm,
-            "bank_builds": st["bank_builds"], "launches": st["launches"],
+            "bank_builds": st["bank_builds"], "launches": st["launches"] - st0["launches"],
+            "shared_launches": st["shared_launches"] - st0["shared_launches"],
+            "max_requests_in_flight": st["max_in_flight"], "top_k": top_k,
             "workload": "synth.serving_requests(seed 191105): lengths 2^18..2^23 bins, zmax even in [50, 300], "
-                        "wmax 3 zmax, dz 2, dw 20, 50% tones, 50% split-BF16; peaks mode"}
+                        "wmax 3 zmax, dz 2, dw 20, 50% tones, 50% split-BF16; per-row peaks and top-k results; "
+                        "request_points_per_s = the path's points over its requests' summed latency"}
 
 
-def batch_leg(J, torch, n_items, slab_rows=128, cand_items=32):
-    """256 uneven de-dispersion-trial spectra (2^20, 2^21, 2^22 bins; zmax 100, wmax 300) through
-    jerk_batch_search: one graph-replayed persistent launch per template slab over all spectra.
-    Spectra are N(0,1) noise generated on the GPU (seeded torch generator) and normalised to unit
-    mean power; plane slabs go to a ring of buffers shared by the items (real HBM writes)."""
+def batch_leg(J, torch, n_items, cand_items=32):
+    """256 uneven de-dispersion-trial spectra (2^20, 2^21, 2^22 bins; zmax 100, wmax 300; 10% with
+    one injected jerk tone) through jerk_batch_search: one graph-replayed launch per template slab
+    over all spectra. Each time series is made on the GPU (seeded noise plus its tone) and turned
+    into its unit-power spectrum by jerk_spectrum_prepare (not timed). Every spectrum writes its own
+    plane region (slab rows x 2n floats each, all in HBM at once), so no two spectra share output
+    memory. The flat launch (the default) is the headline; the persistent kernel is timed beside it."""
     import synth
     specs_meta = synth.batch_spectra_specs(n_items)
-    g = torch.Generator(device="cuda")
-    g.manual_seed(191103)
     specs = []
     for n_samp, seed, tones in specs_meta:
-        x = torch.randn(n_samp, device="cuda", generator=g, dtype=torch.float32)
-        X = torch.fft.rfft(x)[: n_samp // 2]
-        X[0] = 0
-        X = X / torch.sqrt((X[1:].abs() ** 2).mean())
-        specs.append(X.to(torch.complex64).contiguous())
+        x = synth.time_series_device(n_samp, seed, tones)
+        spec, ws_p = J.prepare_spectrum(x)
+        torch.cuda.synchronize()
+        specs.append(spec)
+        del x, ws_p
+    n_tones = sum(1 for m in specs_meta if m[2])
     nmax = max(s.shape[0] for s in specs)
     plan = J.Plan(nmax, 100.0, 300.0, 2.0, 20.0, path="fft")
     t0 = time.perf_counter()
@@ -723,26 +763,32 @@ def batch_leg(J, torch, n_items, slab_rows=128, cand_items=32):
     bank = plan.new_bank()
     plan.build_templates(bank)
     T = plan.info()["n_templates"]
-    ring = [torch.empty((slab_rows, 2 * nmax), dtype=torch.float32, device="cuda") for _ in range(4)]
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    # per-spectrum plane regions: as many rows per slab as fit in 60% of the free memory (<= 64)
+    free, _ = torch.cuda.mem_get_info()
+    row_bytes_all = sum(2 * s.shape[0] * 4 for s in specs)
+    slab_rows = int(max(1, min(64, 0.6 * free // row_bytes_all)))
+    planes = [torch.empty((slab_rows, 2 * s.shape[0]), dtype=torch.float32, device="cuda") for s in specs]
     ws = torch.empty(plan.batch_workspace_bytes(n_items), dtype=torch.uint8, device="cuda")
-    items = [(s, ring[i % len(ring)], None) for i, s in enumerate(specs)]
+    items = [(s, pl, None) for s, pl in zip(specs, planes)]
     pts = sum(2 * s.shape[0] for s in specs) * T
-    # warm-up (captures the graph), then one timed pass over all slabs
-    plan.batch_search(bank, items, ws, 0, min(T, slab_rows), graph=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for t_b in range(0, T, slab_rows):
-        plan.batch_search(bank, items, ws, t_b, min(T, t_b + slab_rows), graph=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    # the same slabs as one flat launch each (a workgroup per tile), also graph-replayed
-    plan.batch_search(bank, items, ws, 0, min(T, slab_rows), graph=True, flat=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for t_b in range(0, T, slab_rows):
-        plan.batch_search(bank, items, ws, t_b, min(T, t_b + slab_rows), graph=True, flat=True)
-    torch.cuda.synchronize()
-    wall_flat = time.perf_counter() - t0
+    out = {"items": n_items, "with_tone": n_tones, "templates": T, "points": pts, "slab_rows": slab_rows,
+           "plane_bytes_resident": slab_rows * row_bytes_all}
+    for name, flat in (("flat", True), ("persistent", False)):
+        # warm-up (captures the graph), then one timed pass over all slabs
+        plan.batch_search(bank, items, ws, 0, min(T, slab_rows), graph=True, flat=flat)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t_b in range(0, T, slab_rows):
+            plan.batch_search(bank, items, ws, t_b, min(T, t_b + slab_rows), graph=True, flat=flat)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = {"wall_s": wall, "points_per_s": pts / wall}
+    out["points_per_s"] = out["flat"]["points_per_s"]
+    out["launches"] = -(-T // slab_rows)
+    del planes, items
+    torch.cuda.empty_cache()
     seg = plan.group(0)["seg_len"]
     # candidates of the first cand_items spectra (k = 6) through jerk_batch_search_candidates: no planes
     cands = None
@@ -768,10 +814,11 @@ def batch_leg(J, torch, n_items, slab_rows=128, cand_items=32):
                  "candidates": int(sum(int(c[2].item()) for c in cl))}
         del cl, cws
     plan.close()
-    return {"items": n_items, "templates": T, "points": pts, "wall_s": wall, "points_per_s": pts / wall,
-            "flat_wall_s": wall_flat, "flat_points_per_s": pts / wall_flat, "candidates_no_plane": cands,
-            "seg_len": seg, "autotune_s": t_tune, "launches": -(-T // slab_rows),
-            "workload": "synth.batch_spectra_specs(256, seed 191103) lengths; GPU noise spectra; zmax 100, wmax 300"}
+    out.update({"candidates_no_plane": cands, "seg_len": seg, "autotune_s": t_tune,
+                "workload": "synth.batch_spectra_specs(256, seed 191103): lengths 2^20..2^22 bins, 10% with one "
+                            "tone; series made on the GPU (synth.time_series_device), spectra by "
+                            "jerk_spectrum_prepare; zmax 100, wmax 300"})
+    return out
 
 
 def main():
@@ -837,6 +884,7 @@ def main():
     avg_t = d["time"] / d["launches"]
     kernel_share = d["time"] / sum(v["time"] for v in ks.values())
     copy = hbm_copy_leg(torch, args.copy_gib) if args.copy_gib > 0 else None
+    peaks = peak_probe()
     tflops = d["flops"] / d["launches"] / avg_t / 1e12
     gbps = d["bytes"] / d["launches"] / avg_t / 1e9
     roof = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBS,
@@ -852,15 +900,16 @@ def main():
         roof["vector_fp32"] = {
             "achieved_tflops": tflops, "flops_counted": "nominal FFT count 5 S log2 S per transform, 6 S per "
                                                         "spectrum product, 3 per kept lag",
-            "peak_tflops": FP32_VECTOR_PUBLISHED_TFLOPS, "frac": tflops / FP32_VECTOR_PUBLISHED_TFLOPS,
-            "nonpacked_peak_tflops": FP32_VECTOR_TFLOPS, "frac_of_nonpacked": tflops / FP32_VECTOR_TFLOPS,
-            "note": "packed FP32 instructions are disabled in all device code, so the FP32 issue ceiling is the "
-                    "non-packed rate 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz; the published 157.3 "
-                    "assumes packed FP32"}
+            "peak_tflops": FP32_VECTOR_PUBLISHED_TFLOPS, "frac": tflops / FP32_VECTOR_PUBLISHED_TFLOPS}
+        if peaks:
+            roof["vector_fp32"]["measured_fma_tflops"] = peaks["fp32_fma"]["TFLOPs"]
+            roof["vector_fp32"]["frac_of_measured_fma"] = tflops / peaks["fp32_fma"]["TFLOPs"]
     else:
         roof["mfma"] = {"achieved_tflops": tflops,
                         "peak_tflops": MFMA_BF16_TFLOPS if d["path"] == 1 else MFMA_FP16_TFLOPS,
                         "frac": tflops / (MFMA_BF16_TFLOPS if d["path"] == 1 else MFMA_FP16_TFLOPS)}
+        if peaks:
+            roof["mfma"]["measured_tflops"] = peaks["mfma_bf16"]["TFLOPs"]
     kernels_out = kernel_table(ks)
 
     paths = {args.path: value}
@@ -914,15 +963,16 @@ def main():
     errors = plane_errors(J, torch) if args.errors else None
     serving = None
     if args.serve_requests > 0:
-        serving = serving_leg(J, torch, args.serve_requests, [float(x) for x in args.serve_load.split(",")])
+        serving = serving_leg(J, torch, args.serve_requests, [float(x) for x in args.serve_load.split(",")],
+                              n_cold=args.serve_cold_requests)
         print("[bench] serving warm " + ", ".join(
             f"load {k}: p50 {v['p50_s']:.3f} s p99 {v['p99_s']:.3f} s" for k, v in serving["warm_poisson"].items()),
             file=sys.stderr, flush=True)
     batch = None
     if args.batch_items > 0:
         batch = batch_leg(J, torch, args.batch_items)
-        print(f"[bench] batch {batch['points_per_s']:.3e} points/s (persistent), "
-              f"{batch['flat_points_per_s']:.3e} (flat)"
+        print(f"[bench] batch {batch['flat']['points_per_s']:.3e} points/s (flat launch), "
+              f"{batch['persistent']['points_per_s']:.3e} (persistent), {batch['slab_rows']} rows per slab"
               + (f", with candidates {batch['candidates_no_plane']['points_per_s']:.3e} "
                  f"({batch['candidates_no_plane']['items']} spectra)" if batch['candidates_no_plane'] else ""),
               file=sys.stderr, flush=True)
@@ -946,7 +996,8 @@ def main():
         top = max(serving["warm_poisson"], key=float)  # the highest offered load
         v = serving["warm_poisson"][top]
         latency = {"load": float(top), "p50_s": v["p50_s"], "p99_s": v["p99_s"], "p99.9_s": v["p99.9_s"],
-                   "requests": v["requests"], "source": "serving leg, warm template cache, Poisson arrivals"}
+                   "requests": v["requests"], "source": "serving leg, warm template cache, Poisson arrivals",
+                   "by_path": {k: v[k] for k in ("fft", "split_bf16") if k in v}}
     line = {
         "metric": "(r,z,w) plane points/s, FP32 vs split-BF16 @<=1e-4 rel err; p50/p99 latency",
         "value": value,
@@ -984,6 +1035,7 @@ def main():
         "kernels": kernels_out,
         "kernels_other_paths": kernels_by_path,
         "hbm_measured": copy,
+        "arithmetic_measured": peaks,
         "serving": serving,
         "latency": latency,
         "batched_256_spectra": batch,

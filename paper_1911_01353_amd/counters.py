@@ -6,9 +6,12 @@
 Sums every counter over the matching dispatches (per kernel name, or all together), prints the
 per-dispatch averages, and the derived figures the counters allow:
 
-- MFMA busy: SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 256 CUs x 4 SIMDs);
-- MFMA rate: 512 flops per SQ_INSTS_VALU_MFMA_MOPS_{BF16,F16} over the GRBM_GUI_ACTIVE time
-  at 2.4 GHz, against the 2.5 PFLOP/s dense peak;
+- MFMA work: 512 flops per SQ_INSTS_VALU_MFMA_MOPS_{BF16,F16}; SQ_VALU_MFMA_BUSY_CYCLES counts the
+  busy cycles of every SIMD's matrix unit (one per 1024 bf16 flops), so over a dispatch of known
+  duration (``--duration-ms``, per dispatch, e.g. from HIP events) and shader clock
+  (``--clock-mhz``) the busy fraction is BUSY / (duration x clock x 256 CUs x 4 SIMDs); without a
+  duration, the busy cycles per SIMD-cycle of CU activity, BUSY / (4 SQ_BUSY_CU_CYCLES), are given
+  (GRBM_GUI_ACTIVE does not count one clock of one engine, so it is not used for rates);
 - wave lifetime: SQ_WAVE_CYCLES / SQ_WAVES, and the shares of the wave cycles spent waiting
   (SQ_WAIT_INST_ANY) or issuing VALU work (SQ_ACTIVE_INST_VALU);
 - HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB) as measured (calibration is traffic.py's job).
@@ -22,7 +25,6 @@ import re
 from collections import defaultdict
 
 N_CU = 256
-CLOCK_HZ = 2.4e9
 MFMA_PEAK = 2.5e15
 
 
@@ -38,18 +40,22 @@ def load(paths, rx):
     return {k: {c: list(d.values()) for c, d in v.items()} for k, v in per.items()}
 
 
-def derived(c):
+def derived(c, duration_ms=0.0, clock_mhz=0.0):
     out = {}
     n = max((len(v) for v in c.values()), default=0)
     tot = {k: sum(v) for k, v in c.items()}
-    if "SQ_VALU_MFMA_BUSY_CYCLES" in tot and tot.get("GRBM_GUI_ACTIVE"):
-        out["mfma_busy_frac"] = tot["SQ_VALU_MFMA_BUSY_CYCLES"] / (tot["GRBM_GUI_ACTIVE"] * N_CU * 4)
+    busy = tot.get("SQ_VALU_MFMA_BUSY_CYCLES")
+    if busy is not None and duration_ms > 0 and clock_mhz > 0:
+        simd_cycles = n * duration_ms * 1e-3 * clock_mhz * 1e6 * N_CU * 4
+        out["mfma_busy_frac"] = busy / simd_cycles
+    if busy is not None and tot.get("SQ_BUSY_CU_CYCLES"):
+        out["mfma_busy_per_simd_cycle_of_cu_activity"] = busy / (4 * tot["SQ_BUSY_CU_CYCLES"])
     for dt in ("BF16", "F16"):
         key = f"SQ_INSTS_VALU_MFMA_MOPS_{dt}"
-        if key in tot and tot.get("GRBM_GUI_ACTIVE"):
-            secs = tot["GRBM_GUI_ACTIVE"] / CLOCK_HZ
-            out[f"mfma_{dt.lower()}_TFLOPs"] = 512 * tot[key] / secs / 1e12
-            out[f"mfma_{dt.lower()}_frac_of_peak"] = 512 * tot[key] / secs / MFMA_PEAK
+        if key in tot and duration_ms > 0:
+            rate = 512 * tot[key] / (n * duration_ms * 1e-3)
+            out[f"mfma_{dt.lower()}_TFLOPs"] = rate / 1e12
+            out[f"mfma_{dt.lower()}_frac_of_peak"] = rate / MFMA_PEAK
     if tot.get("SQ_WAVES"):
         if "SQ_WAVE_CYCLES" in tot:
             out["wave_cycles_per_wave"] = tot["SQ_WAVE_CYCLES"] / tot["SQ_WAVES"]
@@ -68,6 +74,8 @@ def main(argv=None):
     ap.add_argument("csv", nargs="+")
     ap.add_argument("--kernel-regex", default=".")
     ap.add_argument("--group-by", choices=["name", "all"], default="name")
+    ap.add_argument("--duration-ms", type=float, default=0.0, help="duration of one dispatch (for rates)")
+    ap.add_argument("--clock-mhz", type=float, default=0.0, help="shader clock during the dispatches")
     ap.add_argument("--title", default="")
     ap.add_argument("--command", default="")
     ap.add_argument("--out", default="")
@@ -89,7 +97,7 @@ def main(argv=None):
         for k in sorted(c):
             v = c[k]
             lines.append(f"  {k:34s} total {sum(v):.6g}  per dispatch {sum(v) / len(v):.6g}  ({len(v)} dispatches)")
-        for k, v in derived(c).items():
+        for k, v in derived(c, a.duration_ms, a.clock_mhz).items():
             lines.append(f"  = {k:32s} {v:.4g}")
     text = "\n".join(lines) + "\n"
     if a.out:

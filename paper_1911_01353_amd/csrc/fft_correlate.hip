@@ -484,10 +484,10 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, i
       } else {
         constexpr int M = E / R1;
         [[maybe_unused]] uint64_t best = 0;
-        // uniform row base; lanes add 32-bit offsets
-        float2* __restrict__ out2 =
-            j.plane ? reinterpret_cast<float2*>(j.plane + row * j.ld) + seg * U : nullptr;
-        const gf2_ptr out2g = j.plane ? (gf2_ptr)(j.plane + row * j.ld) + seg * U : nullptr;  // TABLE
+        // uniform row base; lanes add 32-bit offsets (through a global view: the job may come from
+        // a device-side table)
+        const bool out2 = j.plane != nullptr;
+        const gf2_ptr out2g = j.plane ? (gf2_ptr)(j.plane + row * j.ld) + seg * U : nullptr;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
           const int b = tid + m * TPB;
@@ -498,10 +498,9 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, i
               const float2 vv = v[m * R1 + k];
               const float p0 = P0[m * R1 + k];
               const float p1 = fmaf(vv.x, vv.x, vv.y * vv.y);
-              if (out2) {
-                if constexpr (TABLE) out2g[(unsigned)lag] = f2vec{p0, p1};
-                else out2[(unsigned)lag] = make_float2(p0, p1);
-              }
+              // plane points are written once and never read here: non-temporal stores keep
+              // them from displacing the template spectra and segments in the caches
+              if (out2) __builtin_nontemporal_store(f2vec{p0, p1}, &out2g[(unsigned)lag]);
               if constexpr (KEYS) {
                 const int64_t p = 2 * (seg * U + lag);
                 const uint64_t k0 = peak_key(p0, p), k1 = peak_key(p1, p + 1);

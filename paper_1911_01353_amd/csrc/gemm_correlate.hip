@@ -31,6 +31,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 
 constexpr int kFragKsPad = 8;  // spare row blocks at the end of a group's fragments (see gemm_bank_bytes)
 
@@ -356,7 +357,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int64_t windows_per
             const f32x16& z = acc[r][c];
             const float p0 = fmaf(z[4 * q], z[4 * q], z[4 * q + 1] * z[4 * q + 1]);
             const float p1 = fmaf(z[4 * q + 2], z[4 * q + 2], z[4 * q + 3] * z[4 * q + 3]);
-            if (row) row[j] = make_float2(p0, p1);
+            // written once, never read here: non-temporal, as on the FFT path
+            if (row) __builtin_nontemporal_store(f2v{p0, p1}, reinterpret_cast<f2v*>(row) + j);
             if constexpr (KEYS) {
               const int64_t p = 2 * (col0 + j);
               const uint64_t k0 = ((uint64_t)__float_as_uint(p0) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)p);

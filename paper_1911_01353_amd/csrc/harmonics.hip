@@ -11,7 +11,8 @@
 // One workgroup covers 1024 consecutive outputs of one fundamental row; lane i
 // takes outputs base + k * 256 + i, so harmonic h reads its row at stride h:
 // for h = 1 every load is coalesced, for larger h each cache line serves
-// 32 / h lanes. The plane is read at most once per (fundamental, harmonic) pair
+// 32 / h lanes (the lines' other words belong to no output of this row, so the
+// bytes moved are those of the lines touched, not 4 per read). The plane is read at most once per (fundamental, harmonic) pair
 // that maps onto it, and the harmonic-summed plane is at most 1/H of the
 // plane's width and ~1/H^2 of its rows.
 #include <cmath>
@@ -25,6 +26,7 @@ constexpr int kThreads = 256;
 constexpr int kPerThread = 4;
 constexpr int64_t kTile = kThreads * kPerThread;
 constexpr int kMaxGridY = 65535;
+constexpr int kChunk = 8;
 
 __global__ void __launch_bounds__(kThreads) harmonic_sum_kernel(const float* __restrict__ plane, int64_t ld,
                                                                 int32_t n_z, int32_t i0, int32_t J, int32_t n_zf,
@@ -34,16 +36,36 @@ __global__ void __launch_bounds__(kThreads) harmonic_sum_kernel(const float* __r
   for (int32_t row = blockIdx.y; row < rows; row += gridDim.y) {
     const int32_t di = row % n_zf - n_zf / 2;
     const int32_t dj = row / n_zf - n_wf / 2;
+    // harmonics in chunks of kChunk: every load of a chunk (all outputs of the thread) is issued
+    // before the first add, so a thread keeps kPerThread x kChunk reads in flight; the adds still
+    // run in h order
+    float s[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) s[k] = 0.0f;
+    for (int32_t h0 = 1; h0 <= n_harm; h0 += kChunk) {
+      float v[kPerThread][kChunk];
+#pragma unroll
+      for (int q = 0; q < kChunk; ++q) {
+        const int32_t h = h0 + q;
+        const int32_t hr = h <= n_harm ? h : n_harm;  // rows past the last harmonic are not read
+        const int64_t t = (int64_t)(J + hr * dj) * n_z + (i0 + hr * di);
+        const float* __restrict__ rowp = plane + t * ld;
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+          const int64_t p = (int64_t)blockIdx.x * kTile + k * kThreads + threadIdx.x;
+          v[k][q] = (h <= n_harm && p < n_pf) ? rowp[(int64_t)h * p] : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kChunk; ++q)
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k)
+          if (h0 + q <= n_harm) s[k] += v[k][q];
+    }
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
       const int64_t p = (int64_t)blockIdx.x * kTile + k * kThreads + threadIdx.x;
-      if (p >= n_pf) break;
-      float s = 0.0f;
-      for (int32_t h = 1; h <= n_harm; ++h) {
-        const int64_t t = (int64_t)(J + h * dj) * n_z + (i0 + h * di);
-        s += plane[t * ld + (int64_t)h * p];
-      }
-      out[(int64_t)row * out_ld + p] = s;
+      if (p < n_pf) __builtin_nontemporal_store(s[k], &out[(int64_t)row * out_ld + p]);
     }
   }
 }
