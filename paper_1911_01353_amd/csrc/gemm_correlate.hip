@@ -58,13 +58,21 @@ __host__ __device__ constexpr int win_words(int cols, int taps) {
 template <int CT>
 __host__ __device__ constexpr int window_cols() { return 32 * CT; }
 
-// One wave per workgroup. The wave owns RB row blocks (8 templates each) of the
-// group and a run of consecutive windows of 32*CT outputs. Tap fragments for up
-// to KC k-steps stay in registers; the spectrum window is double-buffered in
-// LDS and the next window's loads are issued before the current window's MFMAs.
-template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT, bool KEYS, int KT>
+// NW = 1: one wave per workgroup. The wave owns RB row blocks (8 templates each)
+// of the group and a run of consecutive windows of 32*CT outputs. Tap fragments
+// for up to KC k-steps stay in registers; the spectrum window is double-buffered
+// in LDS and the next window's loads are issued before the current window's MFMAs.
+// NW > 1 (resident split-BF16, RB = 1): NW waves share one row block, each with
+// its own run of windows; the block's tap fragments are copied once into LDS and
+// read from there at every k-step instead of being held in 64+ registers per wave,
+// which leaves room for a third wave per SIMD.
+// LDS words of a row block's resident split-BF16 tap fragments: kc slots x hi/lo x 64 lanes x uint4
+__host__ __device__ constexpr int lds_a_words(int kc) { return kc * 2 * 64 * 4; }
+
+template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT, bool KEYS, int KT, int NW = 1>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int64_t windows_per_wg, int64_t n_colchunks, int64_t blk,
                                           uint32_t* lds32) {
+  static_assert(NW == 1 || (RB == 1 && SPLIT && RESIDENT), "several waves per workgroup: resident split-BF16 only");
   constexpr int P = SPLIT ? 2 : 1;        // parts of each operand (hi, lo)
   constexpr int NPART = 2 * P;            // LDS part arrays (re/im x hi/lo)
   constexpr int COLS = window_cols<CT>();
@@ -74,9 +82,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int64_t windows_per
   const int ksr = K / 16;      // k-steps over the real parts
   const int WW = win_words(COLS, K);
   const int buf_words = NPART * 2 * WW;
-  const int lane = threadIdx.x;
-  const int64_t cc = blk % n_colchunks;
-  const int tblk = (int)(blk / n_colchunks);
+  const int lane = threadIdx.x & 63;
+  const int wave = NW > 1 ? (int)(threadIdx.x >> 6) : 0;
+  const int64_t ncg = (n_colchunks + NW - 1) / NW;  // column-chunk groups (one chunk per wave)
+  const int64_t cc = (blk % ncg) * NW + wave;
+  const int tblk = (int)(blk / ncg);
+  // NW > 1: the row block's tap fragments [slot][part][lane] (uint4) first, then each wave's
+  // window buffers
+  uint4* const lds_a = reinterpret_cast<uint4*>(lds32);
+  if constexpr (NW > 1) lds32 += lds_a_words(KC) + wave * 2 * (2 * P * 2 * win_words(COLS, K));
   const int n_members = a.m_end - a.m_begin;
   const int rb0 = a.m_begin / 8 + tblk * RB;  // first row block (group-relative)
   const uint16_t* __restrict__ frag = static_cast<const uint16_t*>(a.bank_gemm);
@@ -87,6 +101,19 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int64_t windows_per
   const int64_t win_first = cc * windows_per_wg;
   const int64_t n_win_total = (a.nbins + COLS - 1) / COLS;
   const int64_t win_last = min(win_first + windows_per_wg, n_win_total);
+  if constexpr (NW > 1) {
+    // every wave copies its share of the fragments before any wave may leave
+    constexpr int NI_ = KC / 4 > 0 ? KC / 4 : 1;
+    for (int e = threadIdx.x; e < KC * P * 64; e += 64 * NW) {
+      const int slot = e / (P * 64), pp = (e / 64) % P, ln = e % 64;
+      const int part = slot / (2 * NI_), parity = (slot / NI_) % 2, i = slot % NI_;
+      const int ksp = parity + 2 * i;
+      const int rbg = a.m_begin / 8 + tblk;
+      lds_a[e] = ksp < ksr ? *reinterpret_cast<const uint4*>(frag + ((((int64_t)rbg * KS + part * ksr + ksp) * P + pp) * 64 + ln) * 8)
+                           : make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();
+  }
   if (win_first >= win_last) return;
   const int npos = COLS + K + 8;            // window elements (with alignment slack), <= 64 * MAXLD
 
@@ -147,7 +174,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int64_t windows_per
   constexpr bool REUSE = RESIDENT && SPLIT;
   constexpr int NI = KC / 4 > 0 ? KC / 4 : 1;
   if constexpr (!REUSE && RESIDENT) load_frags(0);
-  if constexpr (REUSE) {
+  if constexpr (REUSE && NW == 1) {
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -203,7 +230,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int64_t windows_per
     }
   };
   auto products = [&](int q, const uint4 (&bhi)[CT], const uint4 (&blo)[CT], f32x16 (&acc)[RB][CT]) {
-    products_with(afr, q, bhi, blo, acc);
+    if constexpr (NW > 1) {
+      // this k-step's hi and lo tap fragments from LDS (slot q)
+      uint4 A1[RB][KC][P];
+#pragma unroll
+      for (int pp = 0; pp < P; ++pp) A1[0][0][pp] = lds_a[(q * P + pp) * 64 + lane];
+      products_with(A1, 0, bhi, blo, acc);
+    } else {
+      products_with(afr, q, bhi, blo, acc);
+    }
   };
 
   // peak keys of this lane's rows (template 2q + lane/32 of each row block), over all its windows
@@ -239,9 +274,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int64_t windows_per
   // 0x0F70: vmcnt 0, expcnt and lgkmcnt unconstrained.
   __builtin_amdgcn_s_waitcnt(0x0F70);
 
+  // The window buffers of a wave are its own: with NW > 1 only the compiler has to keep the LDS
+  // stores and loads in order (a wave's LDS instructions execute in issue order).
+  auto window_sync = [&]() {
+    if constexpr (NW > 1) asm volatile("" ::: "memory");
+    else __syncthreads();
+  };
   load_window(win_first);
   store_window(0);
-  __syncthreads();
+  window_sync();
   for (int64_t win = win_first; win < win_last; ++win) {
     const int buf = (int)((win - win_first) & 1);
     if (win + 1 < win_last) load_window(win + 1);  // in flight during the MFMAs
@@ -371,7 +412,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int64_t windows_per
       }
     }
     if (win + 1 < win_last) store_window(buf ^ 1);
-    __syncthreads();
+    window_sync();
   }
   if constexpr (KEYS) {
     // combine the 32 lanes of each row (lanes l and l + 32 hold different templates)
@@ -395,6 +436,14 @@ template <int RB, int CT, int KC, int MAXLD, bool SPLIT, bool RESIDENT, bool KEY
 __global__ void __launch_bounds__(64, 2) gemm_correlate_kernel(GemmArgs a, int64_t windows_per_wg, int64_t n_colchunks) {
   extern __shared__ uint32_t lds32[];
   gemm_tile<RB, CT, KC, MAXLD, SPLIT, RESIDENT, KEYS, KT>(a, windows_per_wg, n_colchunks, blockIdx.x, lds32);
+}
+
+// NW waves per workgroup sharing one row block's tap fragments in LDS (resident split-BF16).
+template <int CT, int KC, int MAXLD, bool KEYS, int KT, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)))
+gemm_correlate_mw_kernel(GemmArgs a, int64_t windows_per_wg, int64_t n_colchunks) {
+  extern __shared__ uint32_t lds32[];
+  gemm_tile<1, CT, KC, MAXLD, true, true, KEYS, KT, NW>(a, windows_per_wg, n_colchunks, blockIdx.x, lds32);
 }
 
 // Several narrow width groups in one launch (split-BF16 with at most 64 taps, or FP16 with
@@ -560,14 +609,42 @@ void launch_split_streamed(const GemmArgs& a, hipStream_t stream) {
   }
 }
 
+// NW waves per workgroup (gemm_correlate_mw_kernel): workgroups of one row block by NW column
+// chunks, the tap fragments in LDS.
+template <int CT, int KC, int MAXLD, bool KEYS, int KT, int NW>
+void launch_cfg_mw(const GemmArgs& a, hipStream_t stream) {
+  require(a.taps == KT, JERK_EINTERNAL, "GEMM kernel built for another tap count");
+  constexpr int COLS = window_cols<CT>();
+  const GemmGrid gg = gemm_grid(a, 1, CT);
+  const int64_t n_tblk = gg.blocks / gg.n_colchunks;
+  const int64_t blocks = n_tblk * ((gg.n_colchunks + NW - 1) / NW);
+  require(blocks < (1ll << 31), JERK_EINVAL, "search too large for one launch");
+  require(COLS + a.taps + 8 <= 64 * MAXLD, JERK_EINTERNAL, "GEMM window larger than the per-lane load budget");
+  require(2 * a.taps / 16 <= KC, JERK_EINTERNAL, "resident tap fragments exceed the slots");
+  const size_t lds = (size_t)(lds_a_words(KC) + NW * 2 * (2 * 2 * 2 * win_words(COLS, a.taps))) * sizeof(uint32_t);
+  hipLaunchKernelGGL((gemm_correlate_mw_kernel<CT, KC, MAXLD, KEYS, KT, NW>), dim3((unsigned)blocks), dim3(64 * NW), lds,
+                     stream, a, gg.windows_per_wg, gg.n_colchunks);
+}
+
 template <bool KEYS>
 void launch_split_resident(const GemmArgs& a, hipStream_t stream) {
   switch (a.taps) {
     case 16: launch_cfg<1, 4, 4, 4, true, true, KEYS, 16>(a, stream); break;
     case 32: launch_cfg<1, 4, 4, 4, true, true, KEYS, 32>(a, stream); break;
-    case 48: launch_cfg<1, 4, 8, 4, true, true, KEYS, 48>(a, stream); break;
-    case 64: launch_cfg<1, 4, 8, 4, true, true, KEYS, 64>(a, stream); break;
-    case 80: launch_cfg<1, 4, 12, 4, true, true, KEYS, 80>(a, stream); break;
+    // plane launches: four waves per workgroup sharing the tap fragments in LDS (3 waves per SIMD
+    // instead of 2); peak-key launches keep one wave (their keys would spill)
+    case 48:
+      if constexpr (KEYS) launch_cfg<1, 4, 8, 4, true, true, KEYS, 48>(a, stream);
+      else launch_cfg_mw<4, 8, 4, KEYS, 48, 4>(a, stream);
+      break;
+    case 64:
+      if constexpr (KEYS) launch_cfg<1, 4, 8, 4, true, true, KEYS, 64>(a, stream);
+      else launch_cfg_mw<4, 8, 4, KEYS, 64, 4>(a, stream);
+      break;
+    case 80:
+      if constexpr (KEYS) launch_cfg<1, 4, 12, 4, true, true, KEYS, 80>(a, stream);
+      else launch_cfg_mw<4, 12, 4, KEYS, 80, 4>(a, stream);
+      break;
     case 96: launch_cfg<1, 4, 12, 4, true, true, KEYS, 96>(a, stream); break;
     case 112: launch_cfg<1, 2, 16, 4, true, true, KEYS, 112>(a, stream); break;
     default: launch_cfg<1, 2, 16, 4, true, true, KEYS, 128>(a, stream); break;

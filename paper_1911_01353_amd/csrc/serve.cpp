@@ -378,10 +378,12 @@ bool try_admit(jerk_server& s, Req* q) {
 
 // Fills one free slot with units from the active requests; returns whether it launched.
 bool dispatch(jerk_server& s, Slot& sl) {
+  // A request can take a slot once its template bank is built (a long build must not hold
+  // slots). Its keys are cleared on the build stream; the launch stream waits for that on the
+  // device (below), so requests admitted together start together in the next launches.
   std::vector<Req*> ready;
   for (Req* q : s.active)
-    if (!q->failed && q->next_unit < q->units.size() && event_done(s, q->bank->ready) && event_done(s, q->ready))
-      ready.push_back(q);
+    if (!q->failed && q->next_unit < q->units.size() && event_done(s, q->bank->ready)) ready.push_back(q);
   if (ready.empty()) return false;
   const int64_t budget = s.d.tiles_per_launch;
   std::vector<std::pair<FftJob, std::pair<int32_t, int32_t>>> jobs;  // job, (segment length, elements/thread)
