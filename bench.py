@@ -89,7 +89,7 @@ def launch_counts(g, m, nbins):
 
     FFT path (FP32 vector): per segment one forward FFT per template block, per
     (segment, template, phase) a complex multiply (6S), an inverse FFT
-    (5 S log2 S) and the power of the U kept lags (3U); nominal FFT counts.
+    (5 S log2 S) and the power of the U = S - K + 1 kept lags (3U); nominal FFT counts.
     MFMA path: 8 K real flops per output point per product (3 products for
     split-BF16, 1 for FP16).
     Bytes: 4 per plane point written plus 8 per spectrum bin read.
@@ -227,7 +227,9 @@ def peak_probe():
         return None
     out = json.loads(res.stdout)
     out["what"] = ("v_mfma_f32_32x32x16_bf16 and v_fma_f32 loops with no memory traffic over every SIMD at "
-                   "8 waves per SIMD (paper_1911_01353_amd/peakprobe.hip), best of 3, HIP events")
+                   "8 waves per SIMD; plane-like tile stores (U float2 per workgroup, U = 512: whole lines, "
+                   "U = 481: lines shared by tiles), plain and non-temporal "
+                   "(paper_1911_01353_amd/peakprobe.hip), best of 3, HIP events")
     return out
 
 

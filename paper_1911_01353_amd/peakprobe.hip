@@ -2,7 +2,10 @@
 // v_mfma_f32_32x32x16_bf16 (four independent accumulators per wave) and plain FP32 FMA
 // (v_fma_f32, sixteen independent chains per lane; packed FP32 is not used), each in a loop with
 // no memory traffic over every SIMD at 8 waves per SIMD. Also the shader clock during each loop,
-// from the cycle counter against the constant-rate wall clock.
+// from the cycle counter against the constant-rate wall clock. And the write bandwidth of
+// plane-like tiles (a workgroup stores U float2 at offset seg U of one of 256 rows, 8 stores of
+// 64 lanes, as the FFT epilogue does), plain and non-temporal, for U a multiple of 16 (whole
+// 128-byte lines) and U odd (tiles share lines).
 //
 // Prints one JSON object. Built by build.py into peakprobe next to this file; bench.py runs it.
 #include <hip/hip_runtime.h>
@@ -69,6 +72,24 @@ __global__ void __launch_bounds__(256) fma_loop(int iters, float* out, long long
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+// One tile per workgroup: row blk % rows, tile blk / rows of that row.
+template <bool NT>
+__global__ void __launch_bounds__(64) tile_store_kernel(float2* plane, long ld2, int U, int rows, long tiles) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const long blk = blockIdx.x;
+  if (blk >= tiles) return;
+  f2v* out = reinterpret_cast<f2v*>(plane + (blk % rows) * ld2 + (blk / rows) * U);
+  const float v = (float)blk;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int lag = threadIdx.x + 64 * k;
+    if (lag < U) {
+      if (NT) __builtin_nontemporal_store(f2v{v, v}, out + lag);
+      else out[lag] = f2v{v, v};
+    }
+  }
+}
+
 int main() {
   int dev = 0, cus = 0, wall_khz = 0;
   CHECK(hipGetDevice(&dev));
@@ -112,8 +133,36 @@ int main() {
     std::printf(", \"%s\": {\"TFLOPs\": %.1f, \"ms\": %.3f, \"clock_MHz\": %.0f}",
                 kind == 0 ? "mfma_bf16" : "fp32_fma", flops / (best_ms * 1e-3) / 1e12, best_ms, mhz);
   }
-  std::printf("}\n");
   CHECK(hipFree(out));
   CHECK(hipFree(clk));
+  // plane-like stores: 256 rows of 2^22 float2 (8 GiB)
+  const long ld2 = 1L << 22;
+  const int rows = 256;
+  float2* plane = nullptr;
+  CHECK(hipMalloc(&plane, sizeof(float2) * ld2 * rows));
+  std::printf(", \"tile_stores_TBps\": {");
+  const int us[2] = {512, 481};
+  for (int ui = 0; ui < 2; ++ui) {
+    const int U = us[ui];
+    const long tiles = (ld2 / U) * rows;  // seg < ld2 / U: every tile inside its row
+    for (int nt = 0; nt < 2; ++nt) {
+      float best_ms = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        CHECK(hipEventRecord(e0, 0));
+        if (nt) hipLaunchKernelGGL(tile_store_kernel<true>, dim3((unsigned)tiles), dim3(64), 0, 0, plane, ld2, U, rows, tiles);
+        else hipLaunchKernelGGL(tile_store_kernel<false>, dim3((unsigned)tiles), dim3(64), 0, 0, plane, ld2, U, rows, tiles);
+        CHECK(hipGetLastError());
+        CHECK(hipEventRecord(e1, 0));
+        CHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CHECK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) best_ms = ms;
+      }
+      const double bytes = (double)tiles * U * sizeof(float2);
+      std::printf("%s\"U%d_%s\": %.2f", (ui | nt) ? ", " : "", U, nt ? "nt" : "plain", bytes / (best_ms * 1e-3) / 1e12);
+    }
+  }
+  std::printf("}}\n");
+  CHECK(hipFree(plane));
   return 0;
 }
