@@ -54,3 +54,36 @@ def test_noalloc_rejects_more_rows_than_its_array():
         plan.search_peaks_noalloc(torch.empty(256, dtype=torch.uint8, device=dev), spec, out, 0, T)
     assert ei.value.status == J.JERK_EINVAL and "NOALLOC_MAX_ROWS" in str(ei.value)
     plan.close()
+
+
+def test_noalloc_in_a_captured_graph():
+    """Captured once and replayed with a new spectrum copied into the captured buffer before each
+    replay, eager library work in between: every replay's peaks equal jerk_search_peaks's."""
+    import torch
+    dev = device()
+    n = 20000
+    plan = J.Plan(n, 20.0, 60.0, 2.0, 20.0, path="fft")
+    bank = build_bank(plan)
+    T = plan.info()["n_templates"]
+    spec = torch.from_numpy(_spec(n, 70)).to(dev)
+    out = torch.empty((T, 2), dtype=torch.int32, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.search_peaks_noalloc(bank, spec, out)  # first call on the device: the array's address
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.search_peaks_noalloc(bank, spec, out)
+    for rep in range(3):
+        new = torch.from_numpy(_spec(n, 71 + rep)).to(dev)
+        spec.copy_(new)
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        want = plan.search_peaks(bank, new)  # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want[:T].cpu().numpy()), rep
+    plan.close()
