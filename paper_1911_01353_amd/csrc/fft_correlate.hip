@@ -162,14 +162,27 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, const
   }
 }
 
-// Largest key of the lanes of a workgroup (TPB threads); returned to every thread.
+// Largest 32-bit value of the 64 lanes of a wave, the same in every lane: rows of 16 lanes by
+// DPP (pairs, quads, rotations by 4 and 8), then the four row maxima from lanes 0, 16, 32, 48.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x124, 0xF, 0xF, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false));
+  const uint32_t a = max((uint32_t)__builtin_amdgcn_readlane((int)x, 0), (uint32_t)__builtin_amdgcn_readlane((int)x, 16));
+  const uint32_t b = max((uint32_t)__builtin_amdgcn_readlane((int)x, 32), (uint32_t)__builtin_amdgcn_readlane((int)x, 48));
+  return max(a, b);
+}
+
+// Largest key of the lanes of a workgroup (TPB threads); returned to every thread. Within a
+// wave the high words (power bits) are reduced first, then the low words of the lanes that
+// hold the largest high word. Entered by every lane.
 template <int TPB>
 __device__ __forceinline__ uint64_t block_max_key(uint64_t k, uint64_t* red) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const uint64_t o = __shfl_xor(k, off, 64);
-    k = o > k ? o : k;
-  }
+  const uint32_t hi = (uint32_t)(k >> 32);
+  const uint32_t mh = wave_max_u32(hi);
+  const uint32_t ml = wave_max_u32(hi == mh ? (uint32_t)k : 0u);
+  k = ((uint64_t)mh << 32) | ml;
   if constexpr (TPB > 64) {
     static_assert(TPB <= 512, "reduction buffer holds 8 waves");
     const int wave = threadIdx.x >> 6;
@@ -483,44 +496,66 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, i
                                       wsum, n_hit, tid);
       } else {
         constexpr int M = E / R1;
-        [[maybe_unused]] uint64_t best = 0;
+        // KEYS: this lane's best power bits and 2c + phase of the column c holding it; columns
+        // are visited in increasing lag order and only a strictly larger power replaces the
+        // best, so equal powers keep the lowest plane index (the order of peak_key)
+        [[maybe_unused]] uint32_t bb = 0;
+        [[maybe_unused]] int bc = -1;
         // uniform row base; lanes add 32-bit offsets (through a global view: the job may come from
         // a device-side table)
         const bool out2 = j.plane != nullptr;
         const gf2_ptr out2g = j.plane ? (gf2_ptr)(j.plane + row * j.ld) + seg * U : nullptr;
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-          const int b = tid + m * TPB;
-#pragma unroll
-          for (int k = 0; k < R1; ++k) {
-            const int lag = b + k * (S / R1);
-            if (lag < lag_lim) {
-              const float2 vv = v[m * R1 + k];
-              const float p0 = P0[m * R1 + k];
-              const float p1 = fmaf(vv.x, vv.x, vv.y * vv.y);
-              // plane points are written once and never read here: non-temporal stores keep
-              // them from displacing the template spectra and segments in the caches
-              if (out2) __builtin_nontemporal_store(f2vec{p0, p1}, &out2g[(unsigned)lag]);
-              if constexpr (KEYS) {
-                const int64_t p = 2 * (seg * U + lag);
-                const uint64_t k0 = peak_key(p0, p), k1 = peak_key(p1, p + 1);
-                const uint64_t kk = k1 > k0 ? k1 : k0;
-                best = kk > best ? kk : best;
+        for (int i = 0; i < E; ++i) {
+          // column c holds lag tid + c TPB in v[(c mod M) R1 + c / M]; KEYS visits the columns
+          // in order, the plane alone in register order
+          const int e = KEYS ? (i % M) * R1 + i / M : i;
+          const int c = KEYS ? i : i / R1 + (i % R1) * M;
+          const int lag = tid + c * TPB;
+          if (lag < lag_lim) {
+            const float2 vv = v[e];
+            const float p0 = P0[e];
+            const float p1 = fmaf(vv.x, vv.x, vv.y * vv.y);
+            // plane points are written once and never read here: non-temporal stores keep
+            // them from displacing the template spectra and segments in the caches
+            if (out2) __builtin_nontemporal_store(f2vec{p0, p1}, &out2g[(unsigned)lag]);
+            if constexpr (KEYS) {
+              const uint32_t u0 = __float_as_uint(p0), u1 = __float_as_uint(p1);
+              if (c == 0 || u0 > bb) {
+                bb = u0;
+                bc = 2 * c;
+              }
+              if (u1 > bb) {
+                bb = u1;
+                bc = 2 * c + 1;
               }
             }
           }
         }
+        [[maybe_unused]] uint64_t best = 0;
         if constexpr (KEYS) {
+          if (bc >= 0) {
+            const int64_t p = 2 * (seg * U + tid) + (int64_t)(bc >> 1) * (2 * TPB) + (bc & 1);
+            best = peak_key(__uint_as_float(bb), p);
+          }
           best = block_max_key<TPB>(best, red);
           if (tid == 0) {
             if (j.rmax_ld == 0) atomicMax(reinterpret_cast<unsigned long long*>(j.row_max + row), (unsigned long long)best);
             else j.row_max[row * j.rmax_ld + seg] = best;
           }
-          // per-segment keys: the last segment's tile also clears the row's keys past this
-          // group's segment count, so a row holds no stale keys from an earlier spectrum
-          if (j.rmax_ld != 0 && seg == j.n_seg - 1)
-            for (int64_t q = j.n_seg + tid; q < j.rmax_ld; q += TPB) j.row_max[row * j.rmax_ld + q] = 0;
         }
+      }
+    }
+  }
+  // per-segment keys: the last segment's tile also clears its rows' keys past this group's
+  // segment count, so a row holds no stale keys from an earlier spectrum (after the template
+  // loop, where it costs no registers of the FFTs)
+  if constexpr (KEYS && CAND == 0) {
+    if (j.rmax_ld != 0 && seg == j.n_seg - 1) {
+      for (int mm = m0; mm < m1; ++mm) {
+        const int t = TABLE ? ((gci32_ptr)j.members)[mm] : j.members[mm];
+        const int64_t row = j.row_by_member ? (int64_t)(mm - j.row_base) : (int64_t)(t - j.t_begin);
+        for (int64_t q = j.n_seg + tid; q < j.rmax_ld; q += TPB) j.row_max[row * j.rmax_ld + q] = 0;
       }
     }
   }

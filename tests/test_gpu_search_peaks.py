@@ -46,6 +46,34 @@ def test_peaks_equal_plane_row_maxima(path):
     plan.close()
 
 
+@pytest.mark.parametrize("kind", ["zeros", "constant"])
+@pytest.mark.parametrize("path", ["fft", "split_bf16"])
+def test_peaks_ties_go_to_the_lowest_index(kind, path):
+    """Spectra whose planes hold many exactly equal powers: all zero (every point of every row
+    ties, so each row's peak is index 0) and constant (equal segment inputs give bit-equal
+    powers at the same offset of different segments). The reduction over lanes, columns and
+    segments must keep the first of equal powers, as the argmax of the plane does."""
+    import torch
+    dev = device()
+    n = 20011
+    plan = J.Plan(n, 20.0, 60.0, 2.0, 20.0, path=path)
+    bank = build_bank(plan)
+    spec_np = np.zeros(n, np.complex64) if kind == "zeros" else np.full(n, 1 - 0.5j, np.complex64)
+    T = plan.info()["n_templates"]
+    plane = gpu_plane(plan, bank, spec_np)
+    wp, wi = _row_peaks(plane)
+    if kind == "zeros":
+        assert not wp.any() and not wi.any()
+    else:
+        # ties do occur: some row holds its maximum at more than one index
+        assert any(np.count_nonzero(plane[r] == wp[r]) > 1 for r in range(T))
+    got = J.peaks_numpy(plan.search_peaks(bank, torch.from_numpy(spec_np).to(dev)), T)
+    torch.cuda.synchronize()
+    assert np.array_equal(got["power"].view(np.uint32), wp.view(np.uint32))
+    assert np.array_equal(got["p"].astype(np.int64), wi)
+    plan.close()
+
+
 def test_peaks_graph_replays():
     import torch
     dev = device()
