@@ -46,6 +46,20 @@ __device__ __forceinline__ uint16_t f16_bits(float x) {
   return __builtin_bit_cast(uint16_t, h);
 }
 
+// Largest 32-bit value of the 32-lane half of a wave that holds `lane` (lanes 0-31 and 32-63
+// separately), the same in every lane of that half: rows of 16 lanes by DPP (pairs, quads,
+// rotations by 4 and 8), then each half's two row maxima from lanes 0, 16 (32, 48). Entered by
+// every lane.
+__device__ __forceinline__ uint32_t half_wave_max_u32(uint32_t x, int lane) {
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x124, 0xF, 0xF, false));
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false));
+  const uint32_t a = max((uint32_t)__builtin_amdgcn_readlane((int)x, 0), (uint32_t)__builtin_amdgcn_readlane((int)x, 16));
+  const uint32_t b = max((uint32_t)__builtin_amdgcn_readlane((int)x, 32), (uint32_t)__builtin_amdgcn_readlane((int)x, 48));
+  return lane < 32 ? a : b;
+}
+
 // LDS window of one wave: for each part (re_hi, im_hi, re_lo, im_lo; FP16: re, im)
 // two copies of the window, copy s holding element x + s at element index x, so
 // that any 8 consecutive elements starting at x are 4 aligned 32-bit words of
@@ -241,12 +255,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int64_t windows_per
     }
   };
 
-  // peak keys of this lane's rows (template 2q + lane/32 of each row block), over all its windows
-  uint64_t best[KEYS ? RB : 1][4];
+  // Peak of each of this lane's rows (template 2q + lane/32 of each row block) over all its
+  // windows: the best power's bits and 0xFFFFFFFF - p of its plane index (0: no point yet).
+  // Points come in increasing p, so only a strictly larger power replaces the best and equal
+  // powers keep the lowest index, the order of the 64-bit key (bits << 32 | 0xFFFFFFFF - p).
+  uint32_t bhi_k[KEYS ? RB : 1][4], blo_k[KEYS ? RB : 1][4];
 #pragma unroll
   for (int r = 0; r < (KEYS ? RB : 1); ++r)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) best[r][q] = 0;
+    for (int q = 0; q < 4; ++q) bhi_k[r][q] = blo_k[r][q] = 0u;
 
   // Output row of each of this lane's templates (2q + lane/32 of each row
   // block), -1 when it is outside the requested range; fixed for all windows.
@@ -401,11 +418,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int64_t windows_per
             // written once, never read here: non-temporal, as on the FFT path
             if (row) __builtin_nontemporal_store(f2v{p0, p1}, reinterpret_cast<f2v*>(row) + j);
             if constexpr (KEYS) {
-              const int64_t p = 2 * (col0 + j);
-              const uint64_t k0 = ((uint64_t)__float_as_uint(p0) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)p);
-              const uint64_t k1 = ((uint64_t)__float_as_uint(p1) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)(p + 1));
-              const uint64_t kk = k1 > k0 ? k1 : k0;
-              best[r][q] = kk > best[r][q] ? kk : best[r][q];
+              const uint32_t lo0 = 0xFFFFFFFFu - 2u * (uint32_t)(col0 + j);  // p < 2^32 (nbins < 2^31)
+              const uint32_t u0 = __float_as_uint(p0), u1 = __float_as_uint(p1);
+              if (u0 > bhi_k[r][q] || blo_k[r][q] == 0u) {
+                bhi_k[r][q] = u0;
+                blo_k[r][q] = lo0;
+              }
+              if (u1 > bhi_k[r][q]) {
+                bhi_k[r][q] = u1;
+                blo_k[r][q] = lo0 - 1u;
+              }
             }
           }
         }
@@ -420,12 +442,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& a, int64_t windows_per
     for (int r = 0; r < RB; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        uint64_t k = best[r][q];
-#pragma unroll
-        for (int off = 16; off >= 1; off >>= 1) {
-          const uint64_t o = __shfl_xor(k, off, 64);
-          k = o > k ? o : k;
-        }
+        // high words first, then the low words of the lanes holding the largest high word
+        const uint32_t mh = half_wave_max_u32(bhi_k[r][q], lane);
+        const uint32_t ml = half_wave_max_u32(bhi_k[r][q] == mh ? blo_k[r][q] : 0u, lane);
+        const uint64_t k = ((uint64_t)mh << 32) | ml;
         if ((lane & 31) == 0 && orow_of[r][q] >= 0)
           atomicMax(reinterpret_cast<unsigned long long*>(a.row_max + orow_of[r][q]), (unsigned long long)k);
       }

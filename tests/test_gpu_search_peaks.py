@@ -74,6 +74,35 @@ def test_peaks_ties_go_to_the_lowest_index(kind, path):
     plan.close()
 
 
+FFT_VARIANTS = [(512, 8), (1024, 8), (1024, 16), (2048, 8), (2048, 16), (4096, 8), (4096, 16)]
+
+
+@pytest.mark.parametrize("seg,ept", FFT_VARIANTS)
+def test_peaks_every_fft_variant(seg, ept):
+    """The peak-key epilogue of every FFT kernel variant (segment length, elements per thread)
+    against the row maxima of the plane the same variant writes: 8 and 16 templates per block
+    (member ranges that leave the last block part-filled), a noise spectrum with a tone and a
+    constant one (bit-equal powers at equal segment offsets), over a ragged 20011-bin length
+    whose last segment is cut short."""
+    import torch
+    dev = device()
+    n = 20011
+    plan = J.Plan(n, 20.0, 60.0, 2.0, 20.0, path="fft")
+    T = plan.info()["n_templates"]
+    for tpb in (8, 16):
+        for g in range(len(plan.groups())):
+            plan.set_group(g, seg, tpb, "fft", ept)
+        bank = build_bank(plan)
+        for spec_np in (_spectrum(n, 7), np.full(n, 0.75 + 0.25j, np.complex64)):
+            plane = gpu_plane(plan, bank, spec_np)
+            wp, wi = _row_peaks(plane)
+            got = J.peaks_numpy(plan.search_peaks(bank, torch.from_numpy(spec_np).to(dev)), T)
+            torch.cuda.synchronize()
+            assert np.array_equal(got["power"].view(np.uint32), wp.view(np.uint32)), (seg, ept, tpb)
+            assert np.array_equal(got["p"].astype(np.int64), wi), (seg, ept, tpb)
+    plan.close()
+
+
 def test_peaks_graph_replays():
     import torch
     dev = device()
