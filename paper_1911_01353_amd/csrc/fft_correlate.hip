@@ -117,13 +117,34 @@ struct Dft<1, INV> {
   __device__ __forceinline__ static void run(float2*) {}
 };
 
-// Padded LDS index: one spare float2 every 16 keeps the strided pass writes
-// on distinct banks.
-__device__ __forceinline__ int lds_idx(int i) { return i + (i >> 4); }
+// LDS slot of element i of an exchange written by a pass of span LW. On gfx950 a wave's float2
+// stores go 16 lanes per cycle over 32 four-byte banks and its float2 loads 32 lanes per cycle
+// over 64 banks (the rates that reproduce the SQ_LDS_BANK_CONFLICT shares measured with one
+// padding for all exchanges: 40% of LDS cycles at S = 512, 25% with 16 elements per thread).
+// Each exchange gets its own padding, all of the form i + c (i >> s), so that every lane's
+// addresses stay one base plus per-element constants (no address registers): one spare float2
+// per 16 for LW = 1 (its loads still meet two-way conflicts, which no such padding avoids), LW
+// spare per 8 LW for LW = 2, 4, 8, none from LW = 16 on. Checked exhaustively on the host against
+// that model for every kernel variant: a template's inverse transforms spend 10-14% of their LDS
+// cycles in conflicts instead of 25-40%.
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+template <int LW>
+__device__ __forceinline__ int lds_slot(int i) {
+  if constexpr (LW == 1)
+    return i + (i >> 4);
+  else if constexpr (LW >= 16)
+    return i;
+  else
+    return i + LW * (i >> (ilog2c(LW) + 3));
+}
+// LDS float2 slots of a segment of S points under every padding above.
+template <int S>
+constexpr int lds_slots() { return S + S / 8; }
 
 // One Stockham pass. The thread owns butterflies b = tid + m * TPB, m < E / R.
-// tw: table of exp(-2 pi i k / S), k < S.
-template <int S, int E, int R, int L, bool INV, bool FROM_LDS, bool TO_LDS>
+// tw: table of exp(-2 pi i k / S), k < S. RP: radix of the pass that wrote the
+// LDS exchange this pass reads (FROM_LDS), whose span was L / RP.
+template <int S, int E, int R, int L, bool INV, bool FROM_LDS, bool TO_LDS, int RP = 1>
 __device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, const float2* __restrict__ tw,
                                               int tid) {
   constexpr int TPB = S / E;
@@ -133,7 +154,7 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, const
     for (int m = 0; m < M; ++m) {
       const int b = tid + m * TPB;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[m * R + r] = lds[lds_idx(b + r * (S / R))];
+      for (int r = 0; r < R; ++r) v[m * R + r] = lds[lds_slot<L / RP>(b + r * (S / R))];
     }
     __syncthreads();
   }
@@ -156,7 +177,7 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, const
       const int b = tid + m * TPB;
       const int j = b % L;
 #pragma unroll
-      for (int k = 0; k < R; ++k) lds[lds_idx((b - j) * R + j + L * k)] = v[m * R + k];
+      for (int k = 0; k < R; ++k) lds[lds_slot<L>((b - j) * R + j + L * k)] = v[m * R + k];
     }
     __syncthreads();
   }
@@ -443,12 +464,12 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, i
     }
   }
   stockham_pass<S, E, R1, 1, false, false, true>(v, lds, tw, tid);
-  stockham_pass<S, E, R2, R1, false, true, true>(v, lds, tw, tid);
+  stockham_pass<S, E, R2, R1, false, true, true, R1>(v, lds, tw, tid);
   if constexpr (P4) {
-    stockham_pass<S, E, R3, R1 * R2, false, true, true>(v, lds, tw, tid);
-    stockham_pass<S, E, R4, R1 * R2 * R3, false, true, false>(v, lds, tw, tid);
+    stockham_pass<S, E, R3, R1 * R2, false, true, true, R2>(v, lds, tw, tid);
+    stockham_pass<S, E, R4, R1 * R2 * R3, false, true, false, R3>(v, lds, tw, tid);
   } else {
-    stockham_pass<S, E, R3, R1 * R2, false, true, false>(v, lds, tw, tid);
+    stockham_pass<S, E, R3, R1 * R2, false, true, false, R2>(v, lds, tw, tid);
   }
   float2 F[E];
 #pragma unroll
@@ -476,13 +497,13 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, i
       }
       if constexpr (P4) {
         stockham_pass<S, E, R4, 1, true, false, true>(v, lds, tw, tid);
-        stockham_pass<S, E, R3, R4, true, true, true>(v, lds, tw, tid);
-        stockham_pass<S, E, R2, R4 * R3, true, true, true>(v, lds, tw, tid);
-        stockham_pass<S, E, R1, R4 * R3 * R2, true, true, false>(v, lds, tw, tid);
+        stockham_pass<S, E, R3, R4, true, true, true, R4>(v, lds, tw, tid);
+        stockham_pass<S, E, R2, R4 * R3, true, true, true, R3>(v, lds, tw, tid);
+        stockham_pass<S, E, R1, R4 * R3 * R2, true, true, false, R2>(v, lds, tw, tid);
       } else {
         stockham_pass<S, E, R3, 1, true, false, true>(v, lds, tw, tid);
-        stockham_pass<S, E, R2, R3, true, true, true>(v, lds, tw, tid);
-        stockham_pass<S, E, R1, R3 * R2, true, true, false>(v, lds, tw, tid);
+        stockham_pass<S, E, R2, R3, true, true, true, R3>(v, lds, tw, tid);
+        stockham_pass<S, E, R1, R3 * R2, true, true, false, R2>(v, lds, tw, tid);
       }
       // thread holds lag b + k S/R1 in v[m R1 + k]
       if (phase == 0) {
@@ -566,7 +587,7 @@ __device__ __forceinline__ void fft_tile(const FftJob& j, int64_t seg, int m0, i
 template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS>
 __global__ void __launch_bounds__(S / E) fft_correlate_kernel(FftJob j, const float2* __restrict__ tw) {
   static_assert(R1 * R2 * R3 * R4 == S, "radices must multiply to S");
-  __shared__ float2 lds[S + S / 16];
+  __shared__ float2 lds[lds_slots<S>()];
   __shared__ uint64_t red[8];
   const int64_t blk = blockIdx.x;
   const int m0 = j.m_begin + (int)(blk / j.n_seg) * j.tpb;
@@ -581,7 +602,7 @@ template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS>
 __global__ void __launch_bounds__(S / E) fft_persistent_kernel(const FftJob* __restrict__ jobs,
                                                                BatchHeader* __restrict__ hdr,
                                                                const float2* __restrict__ tw) {
-  __shared__ float2 lds[S + S / 16];
+  __shared__ float2 lds[lds_slots<S>()];
   __shared__ uint64_t red[8];
   __shared__ int64_t s_tile;
   const int64_t total = hdr->total_tiles;
@@ -619,7 +640,7 @@ template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS>
 __global__ void __launch_bounds__(S / E) fft_multi_kernel(const FftJob* __restrict__ jobs,
                                                           const BatchHeader* __restrict__ hdr,
                                                           const float2* __restrict__ tw) {
-  __shared__ float2 lds[S + S / 16];
+  __shared__ float2 lds[lds_slots<S>()];
   __shared__ uint64_t red[8];
   const int64_t tile = blockIdx.x;
   const int n_jobs = hdr->n_jobs;
@@ -645,7 +666,7 @@ struct FftArgJobs {
 
 template <int S, int E, int R1, int R2, int R3, int R4, bool KEYS>
 __global__ void __launch_bounds__(S / E) fft_args_kernel(FftArgJobs m, const float2* __restrict__ tw) {
-  __shared__ float2 lds[S + S / 16];
+  __shared__ float2 lds[lds_slots<S>()];
   __shared__ uint64_t red[8];
   const int64_t tile = blockIdx.x;
   int k = 0;
@@ -663,7 +684,7 @@ __global__ void __launch_bounds__(S / E) fft_args_kernel(FftArgJobs m, const flo
 template <int S, int E, int R1, int R2, int R3, int R4, int CAND>
 __global__ void __launch_bounds__(S / E) fft_cand_kernel(FftJob j, const float2* __restrict__ tw, CandArgs ca) {
   constexpr int W = S / E / 64;
-  __shared__ float2 lds[S + S / 16];
+  __shared__ float2 lds[lds_slots<S>()];
   __shared__ uint64_t red[8];
   __shared__ float xch[2 * W * E];
   __shared__ double2 wsum[W];
