@@ -143,13 +143,14 @@ int32_t jerk_plan_set_group(jerk_plan* plan, int32_t g, int32_t seg_len,
 size_t jerk_autotune_scratch_bytes(const jerk_plan* plan, int64_t nbins);
 /* For every width group, times the candidate kernels on up to 64 of the group's templates over
  * the first min(nbins, 2^22) bins of d_spec (a probe plane of up to 2 GiB in d_scratch, larger
- * than the device's caches, so the ranking holds for full-size searches): the FFT path with segment lengths 512..4096
- * (at least twice the group width) and 8 or 16 templates per workgroup, and for
- * JERK_PATH_AUTO plans also the split-BF16 MFMA path. Keeps the fastest per output point
- * (JERK_TUNE_UNIFORM: FFT only, one segment length minimising the estimated total). Call
+ * than the device's caches, so the ranking holds for full-size searches): the FFT path with
+ * segment lengths 512..4096 (at least twice the group width) and 8 or 16 templates per
+ * workgroup (also 4 for groups whose whole launch would give fewer than 4 waves per SIMD),
+ * and for JERK_PATH_AUTO plans also the split-BF16 MFMA path. Keeps the fastest per output
+ * point (JERK_TUNE_UNIFORM: FFT only, one segment length minimising the estimated total). Call
  * before jerk_templates_build; bank_bytes may change. Synchronous (waits on stream). Choices
- * are cached per process by (device, group width, probe size, candidate set). Plans with a
- * fixed MFMA path are left unchanged. */
+ * are cached per process by (device, group width and size, bins, probe size, candidate set).
+ * Plans with a fixed MFMA path are left unchanged. */
 int32_t jerk_plan_autotune(jerk_plan* plan, const void* d_spec, int64_t nbins, void* d_scratch,
                            size_t scratch_bytes, uint32_t flags, hipStream_t stream);
 

@@ -28,13 +28,19 @@ constexpr int32_t kProbeMembers = 64;
 constexpr int64_t kProbeBins = 1 << 22;
 constexpr int kReps = 5;
 constexpr int32_t kSegs[4] = {512, 1024, 2048, 4096};
-constexpr int32_t kTpbs[2] = {8, 16};
+constexpr int32_t kTpbs[3] = {4, 8, 16};
+// Fewer than 8 templates per block pays only where a group's launch is too small to fill the
+// device (small searches: more, smaller workgroups); on full-size groups it only adds forward
+// transforms and spectrum reads, and a 64-template probe does not show that. So 4 is tried only
+// when the whole group at 8 templates per block gives fewer than 4 waves per SIMD.
+constexpr int64_t kFillWaves = 4 * 1024;
 
 struct Cand {
   int32_t path, seg, tpb, ept;
 };
-// (device ordinal, taps, probe members, probe bins, allow MFMA) -> seconds per output point per candidate
-using Key = std::tuple<int, int32_t, int32_t, int64_t, bool>;
+// (device ordinal, taps, probe members, probe bins, allow MFMA, group members, bins)
+//   -> seconds per output point per candidate
+using Key = std::tuple<int, int32_t, int32_t, int64_t, bool, int32_t, int64_t>;
 std::mutex g_mu;
 std::map<Key, std::vector<std::pair<Cand, double>>> g_cache;
 
@@ -113,7 +119,7 @@ void autotune(Plan& p, const void* d_spec, int64_t nbins, void* d_scratch, size_
   for (size_t gi = 0; gi < p.groups.size(); ++gi) {
     const Group& g = p.groups[gi];
     const int32_t m = std::min<int32_t>((int32_t)g.members.size(), kProbeMembers);
-    const Key key{dev, g.taps, m, pb, allow_gemm};
+    const Key key{dev, g.taps, m, pb, allow_gemm, (int32_t)g.members.size(), nbins};
     {
       std::lock_guard<std::mutex> lock(g_mu);
       auto it = g_cache.find(key);
@@ -135,7 +141,12 @@ void autotune(Plan& p, const void* d_spec, int64_t nbins, void* d_scratch, size_
       if (seg >= 2 * g.taps)
         for (int32_t ept : {8, 16})
           if (fft_variant_supported(seg, ept))
-            for (int32_t tpb : kTpbs) cands.push_back({JERK_PATH_FFT_FP32, seg, tpb, ept});
+            for (int32_t tpb : kTpbs) {
+              const int64_t n_seg = (nbins + (seg - g.taps + 1) - 1) / (seg - g.taps + 1);
+              const int64_t waves8 = n_seg * (((int64_t)g.members.size() + 7) / 8) * (seg / ept / 64);
+              if (tpb < 8 && waves8 >= kFillWaves) continue;
+              cands.push_back({JERK_PATH_FFT_FP32, seg, tpb, ept});
+            }
     if (allow_gemm && g.taps <= 512) cands.push_back({JERK_PATH_GEMM_SPLIT_BF16, 0, 0, 0});
     std::vector<std::pair<Cand, double>> res;
     for (const Cand& c : cands) {
