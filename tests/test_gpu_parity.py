@@ -152,8 +152,19 @@ def test_2e22_bins_sampled_rows():
         tone_at.append((j * grid.n_z + i, int(round(2 * rbar))))
     picks = sorted(picks)
     ora = oracle_plane(spec, grid, templates=picks)
-    for path in ("fft", "auto", "split_bf16", "fp16"):
-        plan = J.Plan(n, cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=path)
+    d_spec = torch.from_numpy(spec).cuda()
+    # the plan defaults of each path, the autotuned AUTO plan the bench times, and the FFT
+    # variants that tuning picks at this size set explicitly (512-point segments with 8 elements
+    # per thread up to 208 taps, 2048-point segments with 16 above, 16 templates per block)
+    for path in ("fft", "auto", "split_bf16", "fp16", "auto_tuned", "fft_512_2048"):
+        base = {"auto_tuned": "auto", "fft_512_2048": "fft"}.get(path, path)
+        plan = J.Plan(n, cfg.zmax, cfg.wmax, cfg.dz, cfg.dw, path=base)
+        if path == "auto_tuned":
+            plan.autotune(d_spec)
+        elif path == "fft_512_2048":
+            for g, gi in enumerate(plan.groups()):
+                seg, ept = (512, 8) if gi["taps"] <= 208 else (2048, 16)
+                plan.set_group(g, seg, 16, "fft", ept)
         bank = build_bank(plan)
         got = np.stack([gpu_plane(plan, bank, spec, t, t + 1)[0] for t in picks])
         assert not np.isnan(got).any()
@@ -161,7 +172,7 @@ def test_2e22_bins_sampled_rows():
         del bank
         torch.cuda.empty_cache()
         print(f"2^22 bins {path}: {len(picks)} whole rows, max {s['max']:.3e} rms {s['rms']:.3e}")
-        assert s["max"] <= TOL[path], (path, s)
+        assert s["max"] <= TOL[base], (path, s)
         # each tone's row peaks within a bin of the tone, at the same point as the oracle's row
         for t, p in tone_at:
             r = picks.index(t)
@@ -300,7 +311,7 @@ def test_fdas_plan_wmax0_zmax200():
         got = full[picks]
         s = error_summary(got, ora)
         print(f"FDAS {path}: max {s['max']:.3e} rms {s['rms']:.3e}")
-        assert s["max"] <= TOL[path], (path, s)
+        assert s["max"] <= TOL[base], (path, s)
         assert peak_index(full) == (t_tone, p_tone), path
         del bank, full
         torch.cuda.empty_cache()
