@@ -32,8 +32,9 @@ constexpr int32_t kTpbs[3] = {4, 8, 16};
 // Fewer than 8 templates per block pays only where a group's launch is too small to fill the
 // device (small searches: more, smaller workgroups); on full-size groups it only adds forward
 // transforms and spectrum reads, and a 64-template probe does not show that. So 4 is tried only
-// when the whole group at 8 templates per block gives fewer than 4 waves per SIMD.
-constexpr int64_t kFillWaves = 4 * 1024;
+// when the whole group at 8 templates per block gives fewer than 4 waves per SIMD (4 SIMDs per
+// compute unit).
+constexpr int64_t kFillWavesPerCu = 4 * 4;
 
 struct Cand {
   int32_t path, seg, tpb, ept;
@@ -96,8 +97,10 @@ void autotune(Plan& p, const void* d_spec, int64_t nbins, void* d_scratch, size_
   const bool uniform = (flags & JERK_TUNE_UNIFORM) != 0;
   const bool allow_gemm = p.desc.path == JERK_PATH_AUTO && !uniform;
   if (p.desc.path == JERK_PATH_GEMM_SPLIT_BF16 || p.desc.path == JERK_PATH_GEMM_FP16) return;  // nothing to choose
-  int dev = 0;
+  int dev = 0, n_cu = 0;
   JERK_HIP_CHECK(hipGetDevice(&dev));
+  JERK_HIP_CHECK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t fill_waves = kFillWavesPerCu * std::max(1, n_cu);
   Scratch s = layout(p, pb, static_cast<char*>(d_scratch));
   for (int i = 0; i < 4; ++i) gen_twiddles(s.tw[i], kSegs[i], stream);
   std::vector<int32_t> out_idx(kProbeMembers);
@@ -144,7 +147,7 @@ void autotune(Plan& p, const void* d_spec, int64_t nbins, void* d_scratch, size_
             for (int32_t tpb : kTpbs) {
               const int64_t n_seg = (nbins + (seg - g.taps + 1) - 1) / (seg - g.taps + 1);
               const int64_t waves8 = n_seg * (((int64_t)g.members.size() + 7) / 8) * (seg / ept / 64);
-              if (tpb < 8 && waves8 >= kFillWaves) continue;
+              if (tpb < 8 && waves8 >= fill_waves) continue;
               cands.push_back({JERK_PATH_FFT_FP32, seg, tpb, ept});
             }
     if (allow_gemm && g.taps <= 512) cands.push_back({JERK_PATH_GEMM_SPLIT_BF16, 0, 0, 0});
