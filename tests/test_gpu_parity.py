@@ -311,7 +311,7 @@ def test_fdas_plan_wmax0_zmax200():
         got = full[picks]
         s = error_summary(got, ora)
         print(f"FDAS {path}: max {s['max']:.3e} rms {s['rms']:.3e}")
-        assert s["max"] <= TOL[base], (path, s)
+        assert s["max"] <= TOL[path], (path, s)
         assert peak_index(full) == (t_tone, p_tone), path
         del bank, full
         torch.cuda.empty_cache()
