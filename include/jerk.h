@@ -144,8 +144,8 @@ size_t jerk_autotune_scratch_bytes(const jerk_plan* plan, int64_t nbins);
 /* For every width group, times the candidate kernels on up to 64 of the group's templates over
  * the first min(nbins, 2^22) bins of d_spec (a probe plane of up to 2 GiB in d_scratch, larger
  * than the device's caches, so the ranking holds for full-size searches): the FFT path with
- * segment lengths 512..4096 (at least twice the group width) and 8 or 16 templates per
- * workgroup (also 4 for groups whose whole launch would give fewer than 4 waves per SIMD),
+ * segment lengths 512..4096 (at least twice the group width) and 8, 16, 32 or 64 templates
+ * per workgroup (also 4 for groups whose whole launch would give fewer than 4 waves per SIMD),
  * and for JERK_PATH_AUTO plans also the split-BF16 MFMA path. Keeps the fastest per output
  * point (JERK_TUNE_UNIFORM: FFT only, one segment length minimising the estimated total). Call
  * before jerk_templates_build; bank_bytes may change. Synchronous (waits on stream). Choices

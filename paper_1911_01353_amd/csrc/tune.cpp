@@ -24,11 +24,12 @@
 namespace jerk {
 namespace {
 
-constexpr int32_t kProbeMembers = 64;
-constexpr int64_t kProbeBins = 1 << 22;
-constexpr int kReps = 5;
+constexpr int32_t kProbeMembers = 256;
+constexpr int64_t kProbeBins = 1 << 20;
+constexpr int kRounds = 3;
+constexpr int kLaunchesPerRound = 4;
 constexpr int32_t kSegs[4] = {512, 1024, 2048, 4096};
-constexpr int32_t kTpbs[3] = {4, 8, 16};
+constexpr int32_t kTpbs[5] = {4, 8, 16, 32, 64};
 // Fewer than 8 templates per block pays only where a group's launch is too small to fill the
 // device (small searches: more, smaller workgroups); on full-size groups it only adds forward
 // transforms and spectrum reads, and a 64-template probe does not show that. So 4 is tried only
@@ -196,19 +197,20 @@ void autotune(Plan& p, const void* d_spec, int64_t nbins, void* d_scratch, size_
         gemm_bank_build(p, tmp, s.taps, s.frags, stream);
       }
       run();  // warm-up
-      // the fastest of a few separately timed runs: a run slowed by anything else on the
-      // device (or a clock change) does not decide the choice
+      // the fastest of a few timed rounds of back-to-back launches: a single probe launch lasts
+      // well under a millisecond and varies by tens of percent, more than the candidates differ;
+      // a round keeps the device busy, and a round slowed by anything else does not decide
       float best_ms = 0.f;
-      for (int r = 0; r < kReps; ++r) {
+      for (int r = 0; r < kRounds; ++r) {
         JERK_HIP_CHECK(hipEventRecord(e0, stream));
-        run();
+        for (int l = 0; l < kLaunchesPerRound; ++l) run();
         JERK_HIP_CHECK(hipEventRecord(e1, stream));
         JERK_HIP_CHECK(hipEventSynchronize(e1));
         float ms = 0.f;
         JERK_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
         if (r == 0 || ms < best_ms) best_ms = ms;
       }
-      res.push_back({c, (double)best_ms * 1e-3 / ((double)m * 2.0 * (double)pb)});
+      res.push_back({c, (double)best_ms * 1e-3 / kLaunchesPerRound / ((double)m * 2.0 * (double)pb)});
     }
     {
       std::lock_guard<std::mutex> lock(g_mu);
