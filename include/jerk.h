@@ -87,7 +87,9 @@ typedef struct jerk_plan_desc {
   int32_t margin_bins;         /* half-width margin M (0..256), usually 16             */
   int32_t path;                /* JERK_PATH_*                                          */
   int32_t seg_len;             /* FFT segment length (512, 1024, 2048, 4096) or 0       */
-  int32_t templates_per_block; /* FFT path templates per workgroup (1..64) or 0         */
+  int32_t templates_per_block; /* FFT path templates per workgroup (1..64), or 0: per group the
+                                  largest of 64, 32, 16, 8 whose launch over the whole group
+                                  has 4096 workgroups at nbins, else 4                      */
   int32_t tap_quantum;         /* width-group granularity in taps (16..512, mult of 16) or 0 */
   uint32_t flags;              /* reserved, must be 0                                  */
 } jerk_plan_desc;

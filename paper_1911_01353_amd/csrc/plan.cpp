@@ -54,8 +54,11 @@ void gauss_legendre16(double* x, double* w) {
   }
 }
 
-// Segment length before autotuning: 1024 (measured fastest on gfx950 for
-// every group width up to 336 taps), longer only for wider templates.
+// Segment length before autotuning: 1024 (with 16 elements per thread the
+// fastest single choice on gfx950 for searches without a plane, and within a
+// few percent of the per-group best for plane-writing ones, where the
+// autotuner picks 512 for narrow and 2048 for wide groups), longer only for
+// wider templates.
 int32_t default_seg_len(int32_t taps) {
   const int32_t cand[3] = {1024, 2048, 4096};
   for (int32_t s : cand)
@@ -65,6 +68,19 @@ int32_t default_seg_len(int32_t taps) {
 
 // Elements per thread of the default FFT kernel variant of a segment length.
 int32_t default_ept(int32_t seg_len) { return seg_len == 512 ? 8 : 16; }
+
+// Templates per workgroup before autotuning: the largest of 64, 32, 16, 8 whose
+// launch over the whole group still has 4096 workgroups, else 4. Larger blocks
+// let each segment's forward transform and spectrum reads serve more templates
+// (64 against 16 on the 2^22-bin search: 3.5% faster writing the plane, 7.5%
+// returning peaks); small searches need the smaller blocks to fill the device
+// (2^15 bins: 24.6 us at 4 per block against 63 us at 16).
+int32_t default_tpb(int64_t nbins, int32_t seg_len, int32_t taps, int64_t members) {
+  const int64_t n_seg = (nbins + (seg_len - taps + 1) - 1) / (seg_len - taps + 1);
+  for (int32_t tpb : {64, 32, 16, 8})
+    if (n_seg * ((members + tpb - 1) / tpb) >= 4096) return tpb;
+  return 4;
+}
 
 // Largest group width the split-BF16 path is chosen for under JERK_PATH_AUTO
 // (the FFT path's cost per output is nearly independent of the width, the
@@ -165,7 +181,8 @@ void plan_build(Plan& p, const jerk_plan_desc& d) {
     g.seg_len = d.seg_len ? d.seg_len : default_seg_len(g.taps);
     require(g.taps <= 2048, JERK_EUNSUPPORTED, "template wider than 2048 taps");
     require(g.seg_len >= 2 * g.taps, JERK_EINVAL, "seg_len must be at least twice the widest group's taps");
-    g.tpb = d.templates_per_block ? d.templates_per_block : 16;
+    g.tpb = d.templates_per_block ? d.templates_per_block
+                                  : default_tpb(d.nbins, g.seg_len, g.taps, (int64_t)g.members.size());
     g.ept = default_ept(g.seg_len);
     if (d.path == JERK_PATH_AUTO) {
       g.path = g.taps <= kAutoGemmMaxTaps ? JERK_PATH_GEMM_SPLIT_BF16 : JERK_PATH_FFT_FP32;
