@@ -3,12 +3,15 @@
 // path) that is fastest per output point on this device. Each candidate runs
 // on probe templates of the group (their bank built in caller scratch) over
 // the first bins of the caller's spectrum and is timed with HIP events. The
-// probe is large enough to rank candidates as a full search does: 64 templates
-// over up to 2^22 bins give every candidate thousands of workgroups (the long
-// segments included) and write a 2 GiB plane, far more than the device's
-// last-level cache holds, so stores cost what they cost in a real search. (A
+// probe is large enough to rank candidates as a full search does: up to 256
+// templates over up to 2^20 bins give every candidate thousands of workgroups
+// (the long segments and the large blocks included) and write a 2 GiB plane, far
+// more than the device's last-level cache holds, so stores cost what they cost
+// in a real search; each candidate is timed over rounds of back-to-back launches,
+// since single probe launches vary by more than the candidates differ. (A
 // 32-template probe over 2^20 bins wrote 256 MiB and favoured 512-point segments
-// for groups where 2048-point segments are faster at full size.)
+// for groups where 2048-point segments are faster at full size; a 64-template
+// one could not rank block sizes.)
 // Results are cached per process, keyed by everything that determines them,
 // so a plan with the same group widths tunes once and a cached choice never
 // changes within the process.
@@ -32,7 +35,7 @@ constexpr int32_t kSegs[4] = {512, 1024, 2048, 4096};
 constexpr int32_t kTpbs[5] = {4, 8, 16, 32, 64};
 // Fewer than 8 templates per block pays only where a group's launch is too small to fill the
 // device (small searches: more, smaller workgroups); on full-size groups it only adds forward
-// transforms and spectrum reads, and a 64-template probe does not show that. So 4 is tried only
+// transforms and spectrum reads, which the probe does not show. So 4 is tried only
 // when the whole group at 8 templates per block gives fewer than 4 waves per SIMD (4 SIMDs per
 // compute unit).
 constexpr int64_t kFillWavesPerCu = 4 * 4;
