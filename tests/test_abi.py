@@ -70,6 +70,23 @@ def test_groups_partition_templates_by_width():
         assert g["path"] == (J.PATH_GEMM_SPLIT_BF16 if g["taps"] <= 96 else J.PATH_FFT_FP32)
 
 
+def test_default_templates_per_block_follows_the_launch_size():
+    """Plan default: per group the largest of 64, 32, 16, 8 templates per block whose launch over
+    the whole group has at least 4096 workgroups at the plan's nbins, else 4 (explicit values win)."""
+    for n, z, w in ((1 << 22, 200, 600), (1 << 20, 100, 300), (1 << 15, 20, 60), (9001, 40, 120)):
+        p = J.Plan(n, z, w, 2.0, 20.0, path="fft")
+        for g in p.groups():
+            U = g["seg_len"] - g["taps"] + 1
+            n_seg = -(-n // U)
+            want = next((t for t in (64, 32, 16, 8) if n_seg * -(-g["n_members"] // t) >= 4096), 4)
+            assert g["templates_per_block"] == want, (n, g)
+        p.close()
+    assert {g["templates_per_block"] for g in J.Plan(1 << 22, 200, 600, 2.0, 20.0, path="fft").groups()} == {64}
+    assert {g["templates_per_block"] for g in J.Plan(1 << 15, 20, 60, 2.0, 20.0, path="fft").groups()} == {4}
+    fixed = J.Plan(1 << 22, 200, 600, 2.0, 20.0, path="fft", templates_per_block=16)
+    assert {g["templates_per_block"] for g in fixed.groups()} == {16}
+
+
 def test_bank_layout_grows_with_overrides():
     p = J.Plan(1 << 16, 20, 60, 2.0, 20.0, path="fft")
     b0 = p.info()["bank_bytes"]
